@@ -316,8 +316,9 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     X <- X Q Lam^{-1/2} until max|Lam - I| <= leaf_tol.  Otherwise split at
     s + length // 2, orthogonalize the left half, repeat R = (B X1)^T X2,
     X2 <- X2 - X1 R until max|R| <= int_tol, then orthogonalize the right half.
-    c defaults to min(m, 16).  Directions with Lam <= drop_tol are linearly
-    dependent and are dropped; later columns move forward into their place.
+    c defaults to min(m, 16).  The columns are first scaled to unit B-norm;
+    directions with Lam <= drop_tol are then linearly dependent and are
+    dropped; later columns move forward into their place.
 
     ``leaf_passes`` / ``int_passes`` force fixed pass counts (used to check the
     paper's count of global reductions).  ``counters['gram']`` counts Gram
@@ -330,6 +331,13 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     if counters is None:
         counters = {}
     counters.setdefault("gram", 0)
+    if m == 0:
+        return X, 0
+    # "eigenvalues close to zero" is judged on the unit-normalized input:
+    # scale every column to unit B-norm first (exact zero columns are dropped)
+    nrm = np.sqrt(np.maximum(np.sum(X * apply_b(bkind, B, X), axis=0), 0.0))
+    X = X[:, nrm > 0] / nrm[nrm > 0][None, :]
+    m = X.shape[1]
     if m == 0:
         return X, 0
     if c is None:
