@@ -1,0 +1,166 @@
+// Internal interfaces between the HIP kernels (kernels.hip), the host dense
+// linear algebra (dense.cpp) and the solver driver (solver.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gcge {
+
+// A contiguous range of columns of a row-major block: column j of the segment
+// is p[i * ld + j], i = 0 .. n-1, j = 0 .. ncol-1.
+struct Seg {
+    const double *p;
+    int64_t ld;
+    int ncol;
+};
+
+// Up to MAX_SEG segments read as one block (their columns concatenated), e.g.
+// V_u = [X_u, P, W] or [X_c, X_u, P].
+constexpr int MAX_SEG = 4;
+struct Segs {
+    Seg s[MAX_SEG];
+    int nseg = 0;
+    int total() const {
+        int t = 0;
+        for (int i = 0; i < nseg; ++i) t += s[i].ncol;
+        return t;
+    }
+    void add(const double *p, int64_t ld, int ncol) {
+        if (ncol > 0) s[nseg++] = Seg{p, ld, ncol};
+    }
+};
+
+// Sparse matrix in CSR form on the device (int32 indices).
+template <typename T>
+struct DevCsr {
+    int64_t n = 0, nnz = 0;
+    const int32_t *rowptr = nullptr;
+    const int32_t *colind = nullptr;
+    const T *val = nullptr;
+};
+
+// Grow-only device scratch used by the reductions.
+struct Workspace {
+    double *part = nullptr;      // partial sums (also used as float)
+    size_t part_bytes = 0;
+    double *small = nullptr;     // small dense matrices (Gram results, coefficient blocks)
+    size_t small_bytes = 0;
+    double *colvec = nullptr;    // per-column scalars
+    size_t colvec_bytes = 0;
+    int *iflags = nullptr;       // CG counters
+    double *pinned = nullptr;    // pinned host staging (hipHostMalloc)
+    size_t pinned_bytes = 0;
+    hipError_t ensure_part(size_t bytes);
+    hipError_t ensure_small(size_t bytes);
+    hipError_t ensure_colvec(size_t bytes);
+    hipError_t ensure_pinned(size_t bytes);
+    hipError_t ensure_flags();
+    void release();
+};
+
+// ------------------------------------------------------------------ launches
+// All launches are asynchronous on `st`.
+
+// Number of row chunks (work-groups) used by the row-streaming kernels for n rows.
+int row_chunks(int64_t n, int k);
+
+// Y = M X with M = A (mode 0), M = A - sigma_j diag(dg) (mode 1, dg == nullptr:
+// identity), or M = A - sigma_j B on the values vb of a shared pattern (mode 2).
+// red = 0: none; red = 1: partial sums of y^2 and (Bx)^2 per column into part
+// (layout [2][k][nparts]); red = 2: partial sums of z_j . y_j (layout [k][nparts]).
+template <typename T>
+hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, int mode, int red,
+                const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part,
+                int nparts, hipStream_t st);
+
+// out[j] = sum_p part[j * nparts + p] (fixed order); count = number of column vectors.
+template <typename T>
+hipError_t colsum(const T *part, int nparts, int k, double *out, hipStream_t st);
+
+// CG state, one entry per column; all device arrays of length k.
+template <typename T>
+struct CgState {
+    T *rr, *rr0, *alpha, *beta;
+    int *active, *its, *flags;   // flags[0] = columns still iterating, flags[1] = columns updated this iteration
+};
+
+template <typename T>
+hipError_t cg_init(const double *R, int64_t ldr, const double *rscale, int k, int64_t n, T *r, T *p,
+                   T *x, int64_t ld, T *part, int nparts, CgState<T> cs, hipStream_t st);
+template <typename T>
+hipError_t cg_init_finish(const T *part, int nparts, int k, CgState<T> cs, hipStream_t st);
+template <typename T>
+hipError_t cg_alpha(const T *part, int nparts, int k, CgState<T> cs, hipStream_t st);
+template <typename T>
+hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, int nparts, CgState<T> cs,
+                       hipStream_t st);
+template <typename T>
+hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> cs, hipStream_t st);
+template <typename T>
+hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st);
+// SpMM of the CG iteration (q = M p with partial p.q), skipped when flags[0] == 0.
+template <typename T>
+hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int nparts,
+                   const int *flags, hipStream_t st);
+
+// C (m x k, row-major, ldc) = X^T diag(d) Y with X given as segments.
+hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
+                int64_t ldc, Workspace &ws, hipStream_t st);
+
+// Y = alpha * X S + beta * Y; X segments (m = total columns), S device row-major
+// (m x lds), Y n x k.
+hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
+                double *Y, int64_t ldy, hipStream_t st);
+
+// Y[:, j] = scale[j] * X[:, j] (scale == nullptr: copy) with type conversion.
+template <typename TI, typename TO>
+hipError_t copy_cols(int64_t n, int k, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const double *scale,
+                     hipStream_t st);
+
+// Move columns [src, src+cnt) to [dst, dst+cnt), dst < src, in place.
+hipError_t shift_cols_left(int64_t n, double *X, int64_t ld, int dst, int src, int cnt, hipStream_t st);
+
+// Y[:, j] = X[:, perm[j]] (perm device int[k]).
+hipError_t gather_cols(int64_t n, int k, const double *X, int64_t ldx, const int *perm, double *Y, int64_t ldy,
+                       hipStream_t st);
+
+// Entry (i, j) = 2 u - 1 with u the SplitMix64 draw (col0 + j) * n + i of stream seed.
+hipError_t fill_random(int64_t n, int k, int col0, uint64_t seed, double *X, int64_t ld, hipStream_t st);
+
+// Shifted operator values on the union pattern: m = a - theta * b (b == nullptr:
+// m = a, then m[dpos[i]] -= theta * dg[i] when dg != nullptr); m32 = float(m).
+hipError_t shift_values(int64_t nnz, const double *a, const double *b, int64_t n, const int32_t *dpos,
+                        const double *dg, double theta, double *m, float *m32, hipStream_t st);
+
+// gval[e] = sum_i w[i] X[r_e, i] X[c_e, i].
+hipError_t pattern_grad(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *X, int64_t ldx,
+                        int nev, const double *w, double *gval, hipStream_t st);
+
+// gd[i] = sum_j w[j] X[i, j]^2.
+hipError_t diag_grad(int64_t n, const double *X, int64_t ldx, int nev, const double *w, double *gd,
+                     hipStream_t st);
+
+// ------------------------------------------------------------- host dense
+// Symmetric eigensolver: a (n x n, row-major, destroyed), w ascending, z (n x
+// nwant row-major) eigenvectors of the nwant smallest eigenvalues.  Returns 0
+// or -1 when the QL iteration does not converge.
+int sym_eig(int n, double *a, double *w, double *z, int nwant);
+
+// Cyclic Jacobi for tiny matrices (n <= 64): a row-major destroyed, w ascending,
+// v row-major n x n eigenvectors as columns.
+int jacobi_small(int n, double *a, double *w, double *v);
+
+// STEP 5 coefficients (row-major dim x n_new output, returns number of columns kept).
+int p_hat(int dim, int nx, const double *xhat, int shift, int n_old, int n_new, double drop_tol, double *phat);
+
+// C (m x n row-major) = A^T B with A (k x m), B (k x n) row-major.
+void matmul_tn(int k, int m, int n, const double *A, const double *B, double *C);
+// C (m x n row-major) = A B with A (m x k), B (k x n) row-major.
+void matmul_nn(int m, int k, int n, const double *A, const double *B, double *C);
+
+}  // namespace gcge

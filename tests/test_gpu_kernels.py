@@ -1,0 +1,216 @@
+"""Parity of each HIP step of one GCG iteration with the CPU oracle, through
+the C ABI (sizes span several tiles and a ragged tail; edge cases included)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_06552_amd as gg
+    gg._lib.load()
+    return gg
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+RNG = np.random.default_rng(2024)
+
+
+def random_csr(n, per_row, empty_rows=(), seed=0):
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        if i in empty_rows:
+            continue
+        c = np.unique(rng.integers(0, n, per_row))
+        rows += [i] * len(c)
+        cols += c.tolist()
+        vals += rng.standard_normal(len(c)).tolist()
+    rows = np.array(rows)
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    return wl.Csr(n, np.cumsum(rowptr).astype(np.int32), np.array(cols, dtype=np.int32), np.array(vals))
+
+
+def abs_csr(A):
+    return A.with_values(np.abs(A.val))
+
+
+@pytest.mark.parametrize("k", [1, 7, 16, 17, 50, 64, 65, 100, 128, 130])
+def test_spmm_fp64(g, k):
+    A = random_csr(1037, 7, empty_rows=(0, 5, 1036))
+    X = RNG.standard_normal((A.n, k))
+    ld = k + 3
+    Xd = torch.zeros((A.n, ld), dtype=torch.float64, device="cuda")
+    Xd[:, :k] = dev(X)
+    Y = g.spmm(g.DeviceCsr.from_csr(A), Xd[:, :k])
+    ref = orc.spmm(A, X)
+    bound = orc.spmm(abs_csr(A), np.abs(X))
+    assert np.all(np.abs(host(Y) - ref) <= 1e-13 * bound + 1e-300)
+
+
+def test_spmm_stencils_and_fp32(g):
+    for A in (wl.laplace2d_5pt(33), wl.laplace3d_7pt(11), wl.q1_fem(7)[0]):
+        X = RNG.standard_normal((A.n, 10))
+        Ad = g.DeviceCsr.from_csr(A)
+        Y = host(g.spmm(Ad, dev(X)))
+        ref = orc.spmm(A, X)
+        assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(orc.spmm(abs_csr(A), np.abs(X)))
+        X32 = X.astype(np.float32)
+        Y32 = host(g.spmm_f32(Ad, dev(A.val, torch.float32), dev(X32, torch.float32)))
+        ref32 = orc.spmm(A.with_values(A.val.astype(np.float32).astype(np.float64)), X32.astype(np.float64))
+        scale = orc.spmm(abs_csr(A), np.abs(X32.astype(np.float64)))
+        assert np.max(np.abs(Y32 - ref32) / scale) < 1e-6
+
+
+@pytest.mark.parametrize("bkind", ["identity", "diag", "csr_same", "csr_other"])
+def test_shifted_spmm_and_residual(g, bkind):
+    A = wl.laplace3d_7pt(9)
+    n = A.n
+    if bkind == "identity":
+        B, Bd = None, None
+        ok, ob = "identity", None
+    elif bkind == "diag":
+        d = wl.diag_uniform(n)
+        B, Bd, ok, ob = d, dev(d), "diag", d
+    elif bkind == "csr_same":
+        B = A.with_values(np.abs(A.val) / 1000 + 0.01)
+        Bd, ok, ob = g.DeviceCsr.from_csr(B), "csr", B
+    else:
+        B = random_csr(n, 3, seed=9)
+        Bd, ok, ob = g.DeviceCsr.from_csr(B), "csr", B
+    k = 19
+    X = RNG.standard_normal((n, k))
+    sig = RNG.uniform(10, 200, k)
+    Ad = g.DeviceCsr.from_csr(A)
+    Y = host(g.shifted_spmm(Ad, Bd, dev(X), sig))
+    ref = orc.shifted_spmm(A, ok, ob, X, sig)
+    assert np.max(np.abs(Y - ref)) < 1e-12 * np.max(np.abs(ref))
+    R, rn, bn = g.residual(Ad, Bd, dev(X), sig)
+    Rr, rnr, bnr = orc.residual(A, ok, ob, X, sig)
+    assert np.max(np.abs(host(R) - Rr)) < 1e-12 * np.max(np.abs(Rr))
+    assert np.max(np.abs(rn - rnr) / rnr) < 1e-13 and np.max(np.abs(bn - bnr) / bnr) < 1e-13
+
+
+@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (15, 3, 2), (1000, 16, 16), (4099, 17, 5), (20000, 50, 50),
+                                   (12345, 65, 64), (9999, 130, 33), (7000, 350, 50), (3000, 400, 100)])
+def test_gram(g, n, m, k):
+    X = RNG.standard_normal((n, m))
+    Y = RNG.standard_normal((n, k))
+    d = RNG.uniform(0.5, 1.5, n)
+    for dd in (None, d):
+        C = g.gram(dev(X), dev(Y), None if dd is None else dev(dd))
+        ref = orc.gram(X, Y, dd)
+        bound = orc.gram(np.abs(X), np.abs(Y), dd)
+        assert np.all(np.abs(C - ref) <= 1e-13 * bound + 1e-300)
+    C1 = g.gram(dev(X), dev(Y))
+    C2 = g.gram(dev(X), dev(Y))
+    assert np.array_equal(C1, C2)   # fixed summation order
+
+
+@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (63, 5, 3), (1000, 16, 16), (4099, 50, 50), (5000, 450, 350),
+                                   (777, 100, 130)])
+def test_gemm_update(g, n, m, k):
+    X = RNG.standard_normal((n, m))
+    S = RNG.standard_normal((m, k))
+    Y0 = RNG.standard_normal((n, k))
+    Y = g.gemm_update(dev(X), S, dev(Y0), alpha=-1.5, beta=0.5)
+    ref = -1.5 * (X @ S) + 0.5 * Y0
+    bound = 1.5 * (np.abs(X) @ np.abs(S)) + 0.5 * np.abs(Y0)
+    assert np.all(np.abs(host(Y) - ref) <= 1e-13 * bound)
+
+
+def test_gemm_in_place_row_transform(g):
+    n, k = 3001, 16
+    X = RNG.standard_normal((n, k))
+    S = RNG.standard_normal((k, 12))
+    Xd = dev(X)
+    g.gemm_update(Xd, S, Xd[:, :12])
+    out = host(Xd)[:, :12]
+    assert np.max(np.abs(out - X @ S)) <= 1e-13 * np.max(np.abs(X) @ np.abs(S))
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 5, 30])
+def test_cg_fp64_matches_oracle(g, maxit):
+    A = wl.laplace3d_7pt(10)
+    d = wl.diag_uniform(A.n)
+    R = RNG.standard_normal((A.n, 12))
+    theta = 25.0
+    D, its = g.cg(g.DeviceCsr.from_csr(A), dev(d), theta, dev(R), maxit=maxit, rel_tol=1e-2)
+    ref, its_r = orc.cg_columnwise(A, "diag", d, theta, R, maxit=maxit, rel_tol=1e-2)
+    assert np.array_equal(its, its_r)
+    assert np.max(np.abs(host(D) - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_cg_mixed_precision_close_to_oracle(g):
+    A = wl.laplace3d_7pt(10)
+    R = RNG.standard_normal((A.n, 10))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), None, 0.0, dev(R), maxit=8, rel_tol=0.0, precision="mixed")
+    ref, _ = orc.cg_columnwise(A, "identity", None, 0.0, R, maxit=8, rel_tol=0.0)
+    assert np.max(np.abs(host(D) - ref)) < 1e-4 * np.max(np.abs(ref))
+    assert np.all(its == 8)
+
+
+def test_cg_breakdown_freezes_columns(g):
+    A = wl.laplace2d_5pt(10)
+    R = RNG.standard_normal((A.n, 3))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), None, 1e7, dev(R), maxit=30)
+    assert np.all(its == 0) and np.all(host(D) == 0)
+
+
+@pytest.mark.parametrize("bkind", ["identity", "diag", "csr"])
+def test_orth_invariants_and_kept_count(g, bkind):
+    A, Bq = wl.q1_fem(9)
+    n = A.n
+    if bkind == "identity":
+        Bd, ok, ob = None, "identity", None
+    elif bkind == "diag":
+        d = wl.diag_uniform(n)
+        Bd, ok, ob = dev(d), "diag", d
+    else:
+        Bd, ok, ob = g.DeviceCsr.from_csr(Bq), "csr", Bq
+    Q0 = RNG.standard_normal((n, 30))
+    Q, kq = orc.recursive_orth_svd(Q0, ok, ob)
+    W0 = RNG.standard_normal((n, 41))
+    W0[:, 7] = W0[:, 3]                        # duplicate column
+    W0[:, 20] = Q[:, 5] * 2.0                  # inside span(Q)
+    W0[:, 33] = W0[:, 1] - 0.5 * W0[:, 30]     # dependent across leaves
+    Wd = dev(W0)
+    Wo = host(g.orth(Wd, dev(Q), Bd))
+    kept = Wo.shape[1]
+    ref, kref = orc.deflate(W0, Q, ok, ob)
+    ref, kref = orc.recursive_orth_svd(ref, ok, ob)
+    assert kept == kref == 38
+    BW = orc.apply_b(ok, ob, Wo)
+    assert np.max(np.abs(Wo.T @ BW - np.eye(kept))) < 1e-13
+    assert np.max(np.abs(Q.T @ BW)) < 1e-13
+    # span([Q, Wo]) contains W0
+    V = np.hstack([Q, Wo])
+    proj = V @ (V.T @ orc.apply_b(ok, ob, W0))
+    assert np.max(np.abs(proj - W0)) < 1e-11 * np.max(np.abs(W0))
+
+
+def test_pattern_grad_matches_formula(g):
+    A = wl.varcoef3d_7pt(8)
+    X = RNG.standard_normal((A.n, 37))
+    w = RNG.standard_normal(37)
+    gd = host(g.pattern_grad(g.DeviceCsr.from_csr(A), dev(X), w))
+    ref = orc.eig_grad(A, X, np.ones(37), w)
+    bound = orc.eig_grad(A, np.abs(X), np.ones(37), np.abs(w))
+    assert np.all(np.abs(gd - ref) <= 1e-13 * bound)

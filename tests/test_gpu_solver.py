@@ -1,0 +1,134 @@
+"""End-to-end GCG solves on the GPU against the oracle (reduced grids, element
+by element) and against closed forms / invariants (full grids)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+from closed_forms import lap2d_eigs, lap3d_eigs, q1_eigs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_06552_amd as gg
+    gg._lib.load()
+    return gg
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def to_dev(g, bkind, B):
+    if bkind == "identity":
+        return None
+    if bkind == "diag":
+        return torch.as_tensor(B, dtype=torch.float64, device="cuda")
+    return g.DeviceCsr.from_csr(B)
+
+
+def gpu_solve(g, A, bkind, B, nev, tol=1e-8, **opts):
+    Ad = g.DeviceCsr.from_csr(A)
+    Bd = to_dev(g, bkind, B)
+    with g.Solver(Ad, Bd, nev, tol, **opts) as s:
+        lam, X, st = s.solve()
+    return lam.numpy(), host(X), st
+
+
+def check_pairs(A, bkind, B, lam, X, tol, orth=1e-12):
+    rel = orc.relative_residuals(A, bkind, B, X, lam)
+    assert rel.max() <= tol, rel.max()
+    G = X.T @ orc.apply_b(bkind, B, X)
+    assert np.max(np.abs(G - np.eye(len(lam)))) < orth
+    assert np.all(np.diff(lam) >= -1e-12 * np.abs(lam).max())
+
+
+def compare_vectors(bkind, B, lam_o, X_o, X, nev, gap=1e-8):
+    """Per cluster of the oracle spectrum (relative gap < gap): the GPU vectors
+    span the same subspace (singular values of X^T B X_o near 1)."""
+    i = 0
+    while i < nev:
+        j = i + 1
+        while j < len(lam_o) and abs(lam_o[j] - lam_o[i]) <= gap * abs(lam_o[i]):
+            j += 1
+        if j <= nev:
+            M = X[:, i:j].T @ orc.apply_b(bkind, B, X_o[:, i:j])
+            s = np.linalg.svd(M, compute_uv=False)   # test-only
+            assert s.min() > 1 - 1e-8, (i, j, s)
+        i = j
+
+
+def test_config1_full_grid_closed_form(g):
+    A = wl.laplace2d_5pt(64)
+    lam, X, st = gpu_solve(g, A, "identity", None, 10, block_size=10)
+    ex = lap2d_eigs(64)[:10]
+    assert np.max(np.abs(lam - ex) / ex) < 1e-10
+    check_pairs(A, "identity", None, lam, X, 1e-8)
+    assert st["status"] == 0 and st["max_rel_residual"] <= 1e-8
+
+
+CASES = [
+    ("lap2d_24", lambda: (wl.laplace2d_5pt(24), "identity", None), 10, dict(block_size=10)),
+    ("lap3d_10_diagB", lambda: (wl.laplace3d_7pt(10), "diag", wl.diag_uniform(1000)), 20, dict(block_size=5)),
+    ("lap3d_10_diagB_mixed", lambda: (wl.laplace3d_7pt(10), "diag", wl.diag_uniform(1000)), 20,
+     dict(block_size=5, precision="mixed")),
+    ("q1fem_9_moving", lambda: (*wl.q1_fem(9)[:1], "csr", wl.q1_fem(9)[1]), 40, dict(block_size=8, moving=1)),
+    ("q1fem_9", lambda: (*wl.q1_fem(9)[:1], "csr", wl.q1_fem(9)[1]), 24, dict(block_size=6)),
+    ("varcoef_10", lambda: (wl.varcoef3d_7pt(10), "identity", None), 10, dict(block_size=3)),
+]
+
+
+@pytest.mark.parametrize("name,make,nev,opts", CASES, ids=[c[0] for c in CASES])
+def test_reduced_grid_parity_with_oracle(g, name, make, nev, opts):
+    A, bkind, B = make()
+    lam_o, X_o = orc.pencil_eigs(A, bkind, B, nev + 8)
+    lam, X, st = gpu_solve(g, A, bkind, B, nev, **opts)
+    assert np.max(np.abs(lam - lam_o[:nev]) / np.abs(lam_o[:nev])) < 1e-10, (lam - lam_o[:nev])
+    check_pairs(A, bkind, B, lam, X, 1e-8)
+    compare_vectors(bkind, B, lam_o, X_o, X, nev)
+    if opts.get("moving"):
+        assert st["moves"] >= 1
+
+
+def test_deterministic(g):
+    A = wl.laplace3d_7pt(12)
+    d = wl.diag_uniform(A.n)
+    r1 = gpu_solve(g, A, "diag", d, 16, block_size=4)
+    r2 = gpu_solve(g, A, "diag", d, 16, block_size=4)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+
+
+def test_edge_cases(g):
+    # nev == n: the initial block spans the whole space
+    A = wl.laplace2d_5pt(4)
+    lam, X, st = gpu_solve(g, A, "identity", None, 16, block_size=4)
+    assert np.max(np.abs(lam - lap2d_eigs(4)) / lap2d_eigs(4)) < 1e-10
+    # nev = 1
+    A = wl.laplace3d_7pt(7)
+    lam, X, st = gpu_solve(g, A, "identity", None, 1)
+    assert abs(lam[0] - lap3d_eigs(7)[0]) / lam[0] < 1e-10
+    # max_iter reached: status NOT_CONVERGED, best approximations returned
+    Ad = g.DeviceCsr.from_csr(wl.laplace3d_7pt(12))
+    with g.Solver(Ad, None, 10, 1e-12, max_iter=1, block_size=2) as s:
+        lam, X, st = s.solve(raise_not_converged=False)
+    assert st["status"] == 1 and np.all(np.isfinite(lam.numpy()))
+
+
+def test_warm_start_reduces_iterations(g):
+    A = wl.laplace3d_7pt(12)
+    d = wl.diag_uniform(A.n)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, torch.as_tensor(d, device="cuda"), 12, 1e-9, block_size=4) as s:
+        lam, X, st = s.solve()
+        it0 = st["iterations"]
+        s.set_initial_vectors(X.clone())
+        lam2, X2, st2 = s.solve()
+    assert st2["iterations"] < it0
+    assert np.max(np.abs(lam2.numpy() - lam.numpy()) / lam.numpy()) < 1e-10
