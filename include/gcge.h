@@ -84,6 +84,14 @@ typedef struct {
                                 6 final check, 7 total                                    */
     double max_rel_residual; /* max over returned pairs of ||Ax - lam Bx|| / (|lam| ||Bx||) */
     double orth_error;       /* max |X^T B X - I| over the returned vectors               */
+    /* With option "profile" = 1: device time (HIP events on the solver stream
+     * around each launch) summed per kernel class, the number of launches and
+     * the summed column count of the launches.  Classes: 0 CG SpMM (q = (A -
+     * theta B) p with p.q), 1 Ritz rotation / P GEMM (V_u xhat, V_u phat),
+     * 2 Gram products, 3 CG vector updates. */
+    double prof_ms[4];
+    int64_t prof_launches[4];
+    int64_t prof_columns[4];
 } gcge_stats;
 
 /* ------------------------------------------------------------------ solver */
@@ -109,12 +117,15 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *                         0 keeps theta = 0
  *  "seed"         [1]     SplitMix64 seed of the random initial block
  *  "check"        [1]     compute max_rel_residual and orth_error at the end
+ *  "profile"      [0]     time the launches of the main kernel classes with HIP events
+ *                         (fields prof_* of gcge_stats)
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
 
 /* Double options: "tol", "cg_rel_tol" [1e-2] (Section 4.1), "orth_tol" [1e-13]
- * (the "small enough" tests of Algorithm 3), "drop_tol" [1e-20] (eigenvalue of a
- * leaf Gram below which a direction counts as linearly dependent). */
+ * (the "small enough" tests of Algorithm 3), "drop_tol" [1e-8] (eigenvalue of a
+ * leaf Gram of unit-B-norm columns at or below which a direction counts as
+ * linearly dependent and is dropped). */
 int gcge_set_option_d(gcge_handle h, const char *key, double value);
 
 /* Stream on which the solver enqueues all its work (hipStream_t as void*). */

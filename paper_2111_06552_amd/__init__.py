@@ -94,7 +94,8 @@ def _b_args(B):
     return B_DIAG, ctypes.c_void_p(B.data_ptr()), None
 
 
-_INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check"}
+_INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
+             "profile"}
 _DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol"}
 
 

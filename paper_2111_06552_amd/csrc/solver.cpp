@@ -57,6 +57,54 @@ struct Buffers {
     }
 };
 
+// Device time of selected launches, bracketed by HIP events on the launch
+// stream (option "profile").  Events come from a reusable pool; the elapsed
+// times are read once at the end of a solve.
+struct KProf {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    struct Mark {
+        int cls, b, e;
+        int64_t cols;
+    };
+    std::vector<Mark> marks;
+    int record(hipStream_t st) {
+        if (next == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            pool.push_back(e);
+        }
+        const int i = (int)next++;
+        if (hipEventRecord(pool[i], st) != hipSuccess) return -1;
+        return i;
+    }
+    int begin(hipStream_t st) { return on ? record(st) : -1; }
+    void end(int cls, int b, int64_t cols, hipStream_t st) {
+        if (!on || b < 0) return;
+        const int e = record(st);
+        if (e >= 0) marks.push_back(Mark{cls, b, e, cols});
+    }
+    void finish(gcge_stats &S) {
+        for (const Mark &m : marks) {
+            float ms = 0.f;
+            if (hipEventSynchronize(pool[m.e]) == hipSuccess && hipEventElapsedTime(&ms, pool[m.b], pool[m.e]) == hipSuccess) {
+                S.prof_ms[m.cls] += ms;
+                S.prof_launches[m.cls] += 1;
+                S.prof_columns[m.cls] += m.cols;
+            }
+        }
+        marks.clear();
+        next = 0;
+    }
+    void release() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+        marks.clear();
+        next = 0;
+    }
+};
+
 // Column-wise CG driver shared by the solver and gcge_cg.
 template <typename T>
 struct CgRunner {
@@ -66,6 +114,7 @@ struct CgRunner {
     int *pinned_flag;
     hipEvent_t ev;
     std::string &err;
+    KProf *prof = nullptr;
 
     int run(const DevCsr<T> &M, const double *R, int64_t ldr, const double *rscale, int k, int maxit,
             double rel_tol, T *x, T *r, T *p, T *q, int64_t ld, CgState<T> cs, int64_t *total_its) {
@@ -79,11 +128,17 @@ struct CgRunner {
         bool pending = false;
         int it = 0;
         for (; it < maxit; ++it) {
+            int pb = prof ? prof->begin(st) : -1;
             e = cg_spmm<T>(M, p, q, ld, k, part, nparts, cs.flags, st);
+            if (prof) prof->end(0, pb, k, st);
             if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
+            pb = prof ? prof->begin(st) : -1;
             if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, nparts, cs, st);
+            if (prof) prof->end(3, pb, k, st);
             if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
+            pb = prof ? prof->begin(st) : -1;
             if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, r, ld, cs, st);
+            if (prof) prof->end(3, pb, k, st);
             if (e != hipSuccess) return fail(e, "cg iteration");
             if (pinned_flag != nullptr && (it % 4) == 3) {
                 // non-blocking poll of the number of active columns
@@ -151,6 +206,8 @@ struct gcge_handle_s {
     bool m_valid = false, m32_valid = false;
     int *pinned_flag = nullptr;
     hipEvent_t ev = nullptr;
+    int profile = 0;
+    KProf prof;
     // results of the last solve
     bool have_res = false;
     std::vector<double> res_lam;   // ascending
@@ -220,7 +277,9 @@ int gcge_handle_s::gram_host(const Segs &X, const double *Y, int64_t ldy, int k,
     if (m == 0 || k == 0) return GCGE_OK;
     hipError_t e = ws.ensure_small(sizeof(double) * (2 * (size_t)m * k + 64));
     if (e != hipSuccess) return hipfail(e, "workspace");
+    const int pb = prof.begin(st);
     e = gram(op.n, X, Y, ldy, k, d, ws.small, k, ws, st);
+    prof.end(2, pb, (int64_t)m * k, st);
     if (e != hipSuccess) return hipfail(e, "gram");
     e = stg.download(C.data(), ws.small, sizeof(double) * m * k);
     if (e != hipSuccess) return hipfail(e, "download");
@@ -234,7 +293,9 @@ int gcge_handle_s::gemm_host(const Segs &X, const std::vector<double> &S, int k,
     if (e != hipSuccess) return hipfail(e, "workspace");
     double *Sd = ws.small + (size_t)m * k + 32;
     e = stg.upload(Sd, S.data(), sizeof(double) * m * k);
+    const int pb = prof.begin(st);
     if (e == hipSuccess) e = gemm(op.n, X, Sd, k, k, 1.0, 0.0, Y, ldy, st);
+    prof.end(1, pb, (int64_t)m * k, st);
     if (e != hipSuccess) return hipfail(e, "rotation");
     return GCGE_OK;
 }
@@ -277,7 +338,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
     if (!mixed) {
         CgState<double> cs{(double *)cm, (double *)(cm + slot), (double *)(cm + 2 * slot), (double *)(cm + 3 * slot),
                            (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
-        CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err};
+        CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
         DevCsr<double> M{op.n, op.nnz, op.rowptr, op.colind, mval};
         return runner.run(M, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
                           cg_its);
@@ -296,7 +357,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
     if (e != hipSuccess) return hipfail(e, "upload");
     CgState<float> cs{(float *)cm, (float *)(cm + slot), (float *)(cm + 2 * slot), (float *)(cm + 3 * slot),
                       (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
-    CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err};
+    CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
     DevCsr<float> M{op.n, op.nnz, op.rowptr, op.colind, mval32};
     int rc = runner.run(M, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
                         cg_its);
@@ -310,6 +371,9 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     have_res = false;
     gcge_stats S;
     std::memset(&S, 0, sizeof(S));
+    prof.on = profile != 0;
+    prof.marks.clear();
+    prof.next = 0;
     const auto T0 = Clock::now();
     const int64_t n = op.n;
     int bs = (int)(opt_bs > 0 ? opt_bs : std::max(1, nev / 5));
@@ -607,6 +671,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     if (e != hipSuccess) return hipfail(e, "sync");
     S.time_ms[6] = ms_since(tf);
     S.time_ms[7] = ms_since(T0);
+    prof.finish(S);
     have_res = nout == nev;
     last = S;
     if (stats_out) *stats_out = S;
@@ -683,6 +748,7 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "shift") { if (v != 0 && v != 1) return bad(); h->shift = (int)v; }
     else if (k == "seed") { h->seed = (uint64_t)v; }
     else if (k == "check") { if (v != 0 && v != 1) return bad(); h->check = (int)v; }
+    else if (k == "profile") { if (v != 0 && v != 1) return bad(); h->profile = (int)v; }
     else return h->fail(GCGE_ERR_INVALID_ARG, "unknown option " + k);
     return GCGE_OK;
 }
@@ -777,6 +843,7 @@ extern "C" void gcge_destroy(gcge_handle h) {
     h->stg.release();
     if (h->pinned_flag) (void)hipHostFree(h->pinned_flag);
     if (h->ev) (void)hipEventDestroy(h->ev);
+    h->prof.release();
     delete h;
 }
 
