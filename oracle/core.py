@@ -35,7 +35,8 @@ PINS = {
     "residual": "zero residual on closed-form eigenpairs; dense recomputation",
     "cg_columnwise": "Remark rem:shift one-step closed form; n-step termination on SPD n x n; "
                      "correction form equals the initial-guess form (same iterates up to shift)",
-    "deflate": "[X,P]^T B W = 0 and span preservation on random inputs",
+    "deflate": "[X,P]^T B W = 0, unit B-norms, each output column parallel to (I - Q Q^T B) w_j; "
+               "a column inside span(Q) is dropped",
     "recursive_orth_svd": "W^T B W = I, span preservation, dependent-column drop, "
                           "m/4 - 1 Gram count for c = 16 (Section 3.1 count)",
     "modified_block_orth": "W^T B W = I, X0^T B W = 0, span preservation, m + m/b - 1 count (Section 3.1)",
@@ -289,27 +290,40 @@ def cg_columnwise(A, bkind, B, theta, R, maxit=30, rel_tol=1e-2, x0=None):
 # STEP 2: B-orthogonalization
 # ---------------------------------------------------------------------------
 
-def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3):
+def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8):
     """Remove from W its B-components along the B-orthonormal block Q:
     repeat R = Q^T B W, W <- W - Q R until max|R| <= tol (at most max_pass
     passes).  This is the top split of the recursive orthogonalization, where
     the left part [X, P] is already B-orthonormal (Section 3.2 STEP 6, last
-    paragraph; Algorithm 3)."""
+    paragraph; Algorithm 3), and the first loop of Algorithm 2.
+
+    The columns of W are first scaled to unit B-norm.  A column whose squared
+    B-norm falls to drop_tol or below in the first pass lay in span(Q): it is
+    linearly dependent and dropped (later columns move forward); the others are
+    rescaled to unit B-norm.  Returns (W_out, passes)."""
     W = np.array(W, dtype=np.float64)
     passes = 0
     if Q.shape[1] == 0 or W.shape[1] == 0:
         return W, passes
-    for _ in range(max_pass):
+    nrm = np.sqrt(np.maximum(np.sum(W * apply_b(bkind, B, W), axis=0), 0.0))
+    W = W[:, nrm > 0] / nrm[nrm > 0][None, :]
+    for p in range(max_pass):
         Rm = b_gram(bkind, B, Q, W)
         W = W - Q @ Rm
         passes += 1
-        if np.max(np.abs(Rm)) <= tol:
+        if p == 0:
+            nu2 = np.sum(W * apply_b(bkind, B, W), axis=0)
+            keep = nu2 > drop_tol
+            W = W[:, keep] / np.sqrt(nu2[keep])[None, :]
+            if W.shape[1] == 0:
+                break
+        elif np.max(np.abs(Rm)) <= tol:
             break
     return W, passes
 
 
 def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_pass=3,
-                       drop_tol=1e-20, leaf_passes=None, int_passes=None, counters=None):
+                       drop_tol=1e-8, leaf_passes=None, int_passes=None, counters=None):
     """RecursiveOrthSVD (Algorithm 3) of the columns of X in the B inner product.
 
     Columns [s, e) with e - s <= c are a leaf: repeat M = X^T B X, M = Q Lam Q^T,
@@ -318,7 +332,10 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     X2 <- X2 - X1 R until max|R| <= int_tol, then orthogonalize the right half.
     c defaults to min(m, 16).  The columns are first scaled to unit B-norm;
     directions with Lam <= drop_tol are then linearly dependent and are
-    dropped; later columns move forward into their place.
+    dropped; later columns move forward into their place.  (An exact duplicate
+    inside one leaf shows up as an eigenvalue at the rounding floor of M,
+    about 1e-16 ||M||, so the threshold has to sit well above it: 1e-8, a
+    remaining B-norm of 1e-4 of the unit input.)
 
     ``leaf_passes`` / ``int_passes`` force fixed pass counts (used to check the
     paper's count of global reductions).  ``counters['gram']`` counts Gram

@@ -283,10 +283,16 @@ def test_deflate_invariants():
     d = RNG.random(n) + 0.5
     Q = _b_orthonormal(n, 10, d)
     W = RNG.standard_normal((n, 6))
+    W[:, 4] = 3.0 * Q[:, 2] - Q[:, 7]        # inside span(Q): dropped
     Wo, passes = orc.deflate(W, Q, "diag", d)
+    assert Wo.shape[1] == 5
     assert np.max(np.abs(Q.T @ (d[:, None] * Wo))) < 1e-13
-    Rm = np.linalg.lstsq(Q, W - Wo, rcond=None)[0]  # W - Wo lies in span(Q)
-    assert np.max(np.abs(Q @ Rm - (W - Wo))) < 1e-12
+    assert np.max(np.abs(np.sum(Wo * d[:, None] * Wo, axis=0) - 1.0)) < 1e-13
+    # each output column is the B-projection of its input column off span(Q), rescaled
+    Wk = np.delete(W, 4, axis=1)
+    proj = Wk - Q @ (Q.T @ (d[:, None] * Wk))
+    cos = np.sum(proj * d[:, None] * Wo, axis=0) / np.sqrt(np.sum(proj * d[:, None] * proj, axis=0))
+    assert np.max(np.abs(cos - 1.0)) < 1e-12
     assert 1 <= passes <= 3
 
 
