@@ -17,9 +17,11 @@
 
 namespace gcge {
 
+// Threads for a parallel loop of `work` multiply-adds: one below ~16K (the
+// fork/join costs more than the loop), then one per ~8K up to the pool size.
 static inline int nthreads_for(long work) {
-    if (work < 200000) return 1;
-    return omp_get_max_threads();
+    if (work < 16384) return 1;
+    return (int)std::max<long>(1, std::min<long>(omp_get_max_threads(), work / 8192));
 }
 
 // Householder tridiagonalization of the symmetric n x n matrix held in a

@@ -66,17 +66,19 @@ struct Workspace {
 // ------------------------------------------------------------------ launches
 // All launches are asynchronous on `st`.
 
-// Number of row chunks (work-groups) used by the row-streaming kernels for n rows.
-int row_chunks(int64_t n, int k);
+// Upper bound on the number of work-groups (partials per column) a
+// row-streaming kernel launches: partial buffers are sized with it.
+int max_row_parts();
 
 // Y = M X with M = A (mode 0), M = A - sigma_j diag(dg) (mode 1, dg == nullptr:
 // identity), or M = A - sigma_j B on the values vb of a shared pattern (mode 2).
 // red = 0: none; red = 1: partial sums of y^2 and (Bx)^2 per column into part
 // (layout [2][k][nparts]); red = 2: partial sums of z_j . y_j (layout [k][nparts]).
+// *nparts receives the number of partials per column (the launch's grid).
 template <typename T>
 hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, int mode, int red,
                 const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part,
-                int nparts, hipStream_t st);
+                int *nparts, hipStream_t st);
 
 // out[j] = sum_p part[j * nparts + p] (fixed order); count = number of column vectors.
 template <typename T>
@@ -91,13 +93,13 @@ struct CgState {
 
 template <typename T>
 hipError_t cg_init(const double *R, int64_t ldr, const double *rscale, int k, int64_t n, T *r, T *p,
-                   T *x, int64_t ld, T *part, int nparts, CgState<T> cs, hipStream_t st);
+                   T *x, int64_t ld, T *part, int *nparts, CgState<T> cs, hipStream_t st);
 template <typename T>
 hipError_t cg_init_finish(const T *part, int nparts, int k, CgState<T> cs, hipStream_t st);
 template <typename T>
 hipError_t cg_alpha(const T *part, int nparts, int k, CgState<T> cs, hipStream_t st);
 template <typename T>
-hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, int nparts, CgState<T> cs,
+hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, int *nparts, CgState<T> cs,
                        hipStream_t st);
 template <typename T>
 hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> cs, hipStream_t st);
@@ -105,7 +107,7 @@ template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st);
 // SpMM of the CG iteration (q = M p with partial p.q), skipped when flags[0] == 0.
 template <typename T>
-hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int nparts,
+hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int *nparts,
                    const int *flags, hipStream_t st);
 
 // C (m x k, row-major, ldc) = X^T diag(d) Y with X given as segments.

@@ -15,6 +15,8 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 namespace gcge {
 
@@ -33,6 +35,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
 }
 
+// Rows visited by one work-group of a row-streaming kernel.  The rows are
+// split into one contiguous range per XCD (work-groups are dispatched
+// round-robin over the XCDs), and inside that range the XCD's work-groups take
+// interleaved groups of ng rows: the resident work-groups of an XCD sweep one
+// compact front, so the stencil neighbours one or two grid lines back are
+// still in that XCD's L2 when they are gathered again.
+struct RowWalk {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ RowWalk row_walk(int64_t n, int ng) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nx = nb < NXCD ? nb : NXCD;
+    const int x = b % nx, w = b / nx;
+    const int nw = nb / nx + (x < nb % nx ? 1 : 0);
+    const int64_t per = (n + nx - 1) / nx;
+    const int64_t r0 = min(n, (int64_t)x * per), r1 = min(n, r0 + per);
+    return RowWalk{r0 + (int64_t)w * ng, r1, (int64_t)nw * ng};
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -40,13 +61,41 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-int row_chunks(int64_t n, int k) {
-    (void)k;
-    int64_t per = std::max<int64_t>(64, (n + 2047) / 2048);
-    return (int)((n + per - 1) / per);
+static int num_cu() {
+    static const int v = [] {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+            c = 256;
+        return c;
+    }();
+    return v;
 }
 
-static inline int64_t rows_per_chunk(int64_t n, int nparts) { return (n + nparts - 1) / nparts; }
+int max_row_parts() { return num_cu() * 8; }
+
+// Work-groups of 256 threads that are resident at once for `fn` (occupancy
+// query, cached per kernel): row-streaming kernels are launched with exactly
+// that many work-groups (capped by the number of work units), so all of them
+// run in one wave of residency and finish together.
+static int resident_grid(const void *fn, int64_t units) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> cache;
+    int nb = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(fn);
+        if (it != cache.end()) {
+            nb = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 4;
+            nb = std::min(nb, 8);
+            cache[fn] = nb;
+        }
+    }
+    const int64_t g = (int64_t)num_cu() * nb;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, std::max<int64_t>(units, 1)));
+}
 
 // ---------------------------------------------------------------------------
 // SpMM: one group of G lanes per row, lane l of the group owns columns
@@ -63,9 +112,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
     if (skip != nullptr && skip[0] == 0) return;
     constexpr int NG = 256 / G;
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
-    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r0 = (int64_t)chunk * rows_per;
-    const int64_t r1 = min(n, r0 + rows_per);
+    const int chunk = blockIdx.x;
+    const RowWalk rw = row_walk(n, NG);
     int col[CT];
     bool cv[CT];
     T sg[CT];
@@ -79,7 +127,9 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
 #pragma unroll
     for (int t = 0; t < CT; ++t) red1[t] = red2[t] = T(0);
 
-    for (int64_t row = r0 + grp; row < r1; row += NG) {
+    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int64_t row = base + grp;
+        if (row >= rw.end) break;
         int e0 = rowptr[row], e1 = rowptr[row + 1];
         if (G == 64) {
             e0 = __builtin_amdgcn_readfirstlane(e0);
@@ -139,39 +189,364 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
                 s1 += sh[0][g][c];
                 s2 += sh[1][g][c];
             }
-            part[(size_t)c * nparts + chunk] = s1;
-            if (RED == 1) part[(size_t)(k + c) * nparts + chunk] = s2;
+            part[(size_t)c * gridDim.x + chunk] = s1;
+            if (RED == 1) part[(size_t)(k + c) * gridDim.x + chunk] = s2;
         }
     }
+}
+
+// 16-byte vector of V elements (double2, float4) for aligned row segments.
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+    T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> vld(const T *p) {
+    return *reinterpret_cast<const Vec<T, V> *>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void vst(T *p, const Vec<T, V> &x) {
+    *reinterpret_cast<Vec<T, V> *>(p) = x;
+}
+
+// SpMM with 16-byte vector accesses: a group of G lanes per row, lane l owns
+// columns V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 8,
+// all eight gathered vector rows being requested before they are used.
+// Requires 16-byte aligned rows and leading dimensions that cover
+// round_up(k, V) columns (the tail lane may touch padding columns, which are
+// never part of a reduction).
+template <typename T, int G, int V, int MODE, int RED>
+__global__ __launch_bounds__(256) void k_spmmv(int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ colind, const T *__restrict__ va,
+                                               const T *__restrict__ vb, const T *__restrict__ dg,
+                                               const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
+                                               int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
+                                               int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
+                                               const int *__restrict__ skip) {
+    if (skip != nullptr && skip[0] == 0) return;
+    constexpr int NG = 256 / G, U = 8;
+    const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
+    const int chunk = blockIdx.x;
+    const RowWalk rw = row_walk(n, NG);
+    const int c0 = lig * V;
+    const bool on = c0 < k;
+    T sg[V], red1[V], red2[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        sg[v] = (MODE != 0 && c0 + v < k) ? sigma[c0 + v] : T(0);
+        red1[v] = red2[v] = T(0);
+    }
+    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int64_t row = base + grp;
+        if (row >= rw.end) break;
+        const int e0 = rowptr[row], e1 = rowptr[row + 1];
+        Vec<T, V> acc, accb;
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] = accb.v[v] = T(0);
+        for (int e = e0; e < e1; e += U) {
+            int cc[U];
+            T av[U], bv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = e + u < e1;
+                cc[u] = ok ? colind[e + u] : (int)row;
+                av[u] = ok ? va[e + u] : T(0);
+                bv[u] = (MODE == 2 && ok) ? vb[e + u] : T(0);
+            }
+            Vec<T, V> xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (on) {
+                    xv[u] = vld<T, V>(X + (int64_t)cc[u] * ldx + c0);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) xv[u].v[v] = T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc.v[v] = fma(av[u], xv[u].v[v], acc.v[v]);
+                    if (MODE == 2) accb.v[v] = fma(bv[u], xv[u].v[v], accb.v[v]);
+                }
+        }
+        if (!on) continue;
+        T bx[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) bx[v] = T(0);
+        if (MODE == 1) {
+            const Vec<T, V> xs = vld<T, V>(X + row * ldx + c0);
+            const T dw = (dg != nullptr) ? dg[row] : T(1);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                bx[v] = dw * xs.v[v];
+                acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
+            }
+        } else if (MODE == 2) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                bx[v] = accb.v[v];
+                acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
+            }
+        }
+        vst<T, V>(Y + row * ldy + c0, acc);
+        if (RED == 1) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (c0 + v < k) {
+                    red1[v] = fma(acc.v[v], acc.v[v], red1[v]);
+                    red2[v] = fma(bx[v], bx[v], red2[v]);
+                }
+        } else if (RED == 2) {
+            const Vec<T, V> z = vld<T, V>(Z + row * ldz + c0);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (c0 + v < k) red1[v] = fma(acc.v[v], z.v[v], red1[v]);
+        }
+    }
+    if (RED != 0) {
+        __shared__ T sh[2][NG][G * V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            sh[0][grp][c0 + v] = red1[v];
+            sh[1][grp][c0 + v] = red2[v];
+        }
+        __syncthreads();
+        for (int c = tid; c < G * V; c += 256) {
+            if (c >= k) continue;
+            T s1 = T(0), s2 = T(0);
+            for (int g = 0; g < NG; ++g) {
+                s1 += sh[0][g][c];
+                s2 += sh[1][g][c];
+            }
+            part[(size_t)c * gridDim.x + chunk] = s1;
+            if (RED == 1) part[(size_t)(k + c) * gridDim.x + chunk] = s2;
+        }
+    }
+}
+
+// SpMM with the sparsity pattern of each block of RS consecutive rows staged
+// in LDS: the work-group loads the block's row pointers, then its column
+// indices and values with one coalesced sweep, and the row groups gather the
+// vector rows with the indices read from LDS (no per-lane broadcast loads,
+// one dependent global round trip per row instead of three).  Blocks whose
+// nonzeros do not fit the staging area fall back to global index loads.
+template <typename T, int G, int V, int MODE, int RED>
+__global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ colind, const T *__restrict__ va,
+                                               const T *__restrict__ vb, const T *__restrict__ dg,
+                                               const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
+                                               int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
+                                               int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
+                                               const int *__restrict__ skip) {
+    if (skip != nullptr && skip[0] == 0) return;
+    constexpr int NG = 256 / G, U = 8;
+    constexpr int RS = NG > 32 ? NG : 32;   // rows per staged block
+    constexpr int RPG = RS / NG;            // rows per group per block
+    constexpr int CAP = 1024;               // staged nonzeros per block
+    __shared__ int s_rp[RS + 1];
+    __shared__ int s_ci[CAP];
+    __shared__ T s_va[CAP];
+    __shared__ T s_vb[MODE == 2 ? CAP : 1];
+    const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
+    const int chunk = blockIdx.x;
+    const RowWalk rw = row_walk(n, RS);
+    const int c0 = lig * V;
+    const bool on = c0 < k;
+    const int c0l = on ? c0 : 0;   // load column (lanes past k read column 0)
+    T sg[V], red1[V], red2[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        sg[v] = (MODE != 0 && c0 + v < k) ? sigma[c0 + v] : T(0);
+        red1[v] = red2[v] = T(0);
+    }
+    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int nrows = (int)min((int64_t)RS, rw.end - base);
+        for (int t = tid; t <= nrows; t += 256) s_rp[t] = rowptr[base + t];
+        __syncthreads();
+        const int eb = s_rp[0], ne = s_rp[nrows] - eb;
+        const bool staged = ne <= CAP;
+        if (staged) {
+            for (int t = tid; t < ne; t += 256) {
+                s_ci[t] = colind[eb + t];
+                s_va[t] = va[eb + t];
+                if (MODE == 2) s_vb[t] = vb[eb + t];
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < RPG; ++j) {
+            const int lr = j * NG + grp;
+            if (lr >= nrows) break;
+            const int64_t row = base + lr;
+            const int e0 = s_rp[lr] - eb, e1 = s_rp[lr + 1] - eb;
+            Vec<T, V> acc, accb;
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc.v[v] = accb.v[v] = T(0);
+            // Slots past the row end re-read the row's last entry (a valid
+            // address) with a zero weight, and lanes past column k read column
+            // 0: every load is unconditional, so the eight gathers of a batch
+            // are all in flight before the first one is used.
+            for (int e = e0; e < e1; e += U) {
+                int cc[U];
+                T av[U], bv[U];
+                if (staged) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int ee = min(e + u, e1 - 1);
+                        const bool ok = e + u < e1;
+                        cc[u] = s_ci[ee];
+                        const T a = s_va[ee];
+                        av[u] = ok ? a : T(0);
+                        if (MODE == 2) {
+                            const T b = s_vb[ee];
+                            bv[u] = ok ? b : T(0);
+                        } else {
+                            bv[u] = T(0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int ee = eb + min(e + u, e1 - 1);
+                        const bool ok = e + u < e1;
+                        cc[u] = colind[ee];
+                        const T a = va[ee];
+                        av[u] = ok ? a : T(0);
+                        if (MODE == 2) {
+                            const T b = vb[ee];
+                            bv[u] = ok ? b : T(0);
+                        } else {
+                            bv[u] = T(0);
+                        }
+                    }
+                }
+                Vec<T, V> xv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) xv[u] = vld<T, V>(X + (int64_t)cc[u] * ldx + c0l);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        acc.v[v] = fma(av[u], xv[u].v[v], acc.v[v]);
+                        if (MODE == 2) accb.v[v] = fma(bv[u], xv[u].v[v], accb.v[v]);
+                    }
+            }
+            if (!on) continue;
+            T bx[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) bx[v] = T(0);
+            if (MODE == 1) {
+                const Vec<T, V> xs = vld<T, V>(X + row * ldx + c0);
+                const T dw = (dg != nullptr) ? dg[row] : T(1);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    bx[v] = dw * xs.v[v];
+                    acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
+                }
+            } else if (MODE == 2) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    bx[v] = accb.v[v];
+                    acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
+                }
+            }
+            vst<T, V>(Y + row * ldy + c0, acc);
+            if (RED == 1) {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (c0 + v < k) {
+                        red1[v] = fma(acc.v[v], acc.v[v], red1[v]);
+                        red2[v] = fma(bx[v], bx[v], red2[v]);
+                    }
+            } else if (RED == 2) {
+                const Vec<T, V> z = vld<T, V>(Z + row * ldz + c0);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (c0 + v < k) red1[v] = fma(acc.v[v], z.v[v], red1[v]);
+            }
+        }
+        __syncthreads();
+    }
+    if (RED != 0) {
+        __shared__ T sh[2][NG][G * V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            sh[0][grp][c0 + v] = red1[v];
+            sh[1][grp][c0 + v] = red2[v];
+        }
+        __syncthreads();
+        for (int c = tid; c < G * V; c += 256) {
+            if (c >= k) continue;
+            T s1 = T(0), s2 = T(0);
+            for (int g = 0; g < NG; ++g) {
+                s1 += sh[0][g][c];
+                s2 += sh[1][g][c];
+            }
+            part[(size_t)c * gridDim.x + chunk] = s1;
+            if (RED == 1) part[(size_t)(k + c) * gridDim.x + chunk] = s2;
+        }
+    }
+}
+
+template <typename T>
+static inline bool aligned16(const T *p) {
+    return p == nullptr || ((uintptr_t)p % 16) == 0;
 }
 
 template <typename T, int MODE, int RED>
 static hipError_t spmm_dispatch(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, const T *X,
                                 int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part,
-                                int nparts, const int *skip, hipStream_t st) {
-    const int64_t rp = rows_per_chunk(A.n, nparts);
-    dim3 grid(nparts), block(256);
-#define GCGE_SPMM_LAUNCH(G, CT)                                                                          \
-    hipLaunchKernelGGL((k_spmm<T, G, CT, MODE, RED>), grid, block, 0, st, A.n, A.rowptr, A.colind, A.val, \
-                       vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, nparts, rp, skip)
-    if (k <= 16) GCGE_SPMM_LAUNCH(16, 1);
-    else if (k <= 32) GCGE_SPMM_LAUNCH(32, 1);
-    else if (k <= 64) GCGE_SPMM_LAUNCH(64, 1);
-    else GCGE_SPMM_LAUNCH(64, 2);
-#undef GCGE_SPMM_LAUNCH
+                                int *nparts, const int *skip, hipStream_t st) {
+    dim3 block(256);
+    constexpr int V = 16 / sizeof(T);
+    const int kp = (k + V - 1) / V * V;
+    const bool vec = aligned16(X) && aligned16(Y) && aligned16(Z) && ldx % V == 0 && ldy % V == 0 &&
+                     (Z == nullptr || ldz % V == 0) && kp <= ldx && kp <= ldy && (Z == nullptr || kp <= ldz) &&
+                     kp <= 64 * V;
+    const void *fn = nullptr;
+    int units = 1;
+    if (vec) {
+        const int lanes = (k + V - 1) / V;
+        const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
+        const int RS = std::max(256 / G, 32);
+        units = (int)std::min<int64_t>((A.n + RS - 1) / RS, 1 << 30);
+#define GCGE_SPMMS(Gv)                                                                                   \
+    if (G == Gv) {                                                                                       \
+        fn = (const void *)k_spmms<T, Gv, V, MODE, RED>;                                                 \
+        const int g = resident_grid(fn, units);                                                          \
+        if (nparts) *nparts = g;                                                                         \
+        hipLaunchKernelGGL((k_spmms<T, Gv, V, MODE, RED>), dim3(g), block, 0, st, A.n, A.rowptr, A.colind, \
+                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip);     \
+    }
+        GCGE_SPMMS(4) else GCGE_SPMMS(8) else GCGE_SPMMS(16) else GCGE_SPMMS(32) else GCGE_SPMMS(64)
+#undef GCGE_SPMMS
+        return hipGetLastError();
+    }
+    const int G = k <= 16 ? 16 : k <= 32 ? 32 : 64;
+    const int CT = k <= 64 ? 1 : 2;
+    units = (int)std::min<int64_t>((A.n + 256 / G - 1) / (256 / G), 1 << 30);
+#define GCGE_SPMM1(Gv, CTv)                                                                              \
+    if (G == Gv && CT == CTv) {                                                                          \
+        fn = (const void *)k_spmm<T, Gv, CTv, MODE, RED>;                                                \
+        const int g = resident_grid(fn, units);                                                          \
+        if (nparts) *nparts = g;                                                                         \
+        hipLaunchKernelGGL((k_spmm<T, Gv, CTv, MODE, RED>), dim3(g), block, 0, st, A.n, A.rowptr, A.colind, \
+                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip);     \
+    }
+    GCGE_SPMM1(16, 1) else GCGE_SPMM1(32, 1) else GCGE_SPMM1(64, 1) else GCGE_SPMM1(64, 2)
+#undef GCGE_SPMM1
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, int mode, int red, const T *X,
-                int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part, int nparts,
+                int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part, int *nparts,
                 hipStream_t st) {
+    if (nparts) *nparts = 0;
     if (A.n == 0 || k == 0) return hipSuccess;
     if (k > 128) return hipErrorInvalidValue;
-    if (nparts <= 0) {
-        if (red != 0) return hipErrorInvalidValue;
-        nparts = row_chunks(A.n, k);
-    }
+    if (red != 0 && (part == nullptr || nparts == nullptr)) return hipErrorInvalidValue;
 #define GCGE_SPMM_CASE(M, R) \
     if (mode == M && red == R) return spmm_dispatch<T, M, R>(A, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, nparts, nullptr, st)
     GCGE_SPMM_CASE(0, 0);
@@ -186,17 +561,15 @@ hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, in
 
 template hipError_t spmm<double>(const DevCsr<double> &, const double *, const double *, const double *, int, int,
                                  const double *, int64_t, int, double *, int64_t, const double *, int64_t,
-                                 double *, int, hipStream_t);
+                                 double *, int *, hipStream_t);
 template <>
 hipError_t spmm<float>(const DevCsr<float> &A, const float *vb, const float *dg, const float *sigma, int mode,
                        int red, const float *X, int64_t ldx, int k, float *Y, int64_t ldy, const float *Z,
-                       int64_t ldz, float *part, int nparts, hipStream_t st) {
+                       int64_t ldz, float *part, int *nparts, hipStream_t st) {
+    if (nparts) *nparts = 0;
     if (A.n == 0 || k == 0) return hipSuccess;
     if (k > 128) return hipErrorInvalidValue;
-    if (nparts <= 0) {
-        if (red != 0) return hipErrorInvalidValue;
-        nparts = row_chunks(A.n, k);
-    }
+    if (red != 0 && (part == nullptr || nparts == nullptr)) return hipErrorInvalidValue;
     if (mode == 0 && red == 0)
         return spmm_dispatch<float, 0, 0>(A, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, nparts, nullptr, st);
     if (mode == 0 && red == 2)
@@ -205,15 +578,15 @@ hipError_t spmm<float>(const DevCsr<float> &A, const float *vb, const float *dg,
 }
 
 template <typename T>
-hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int nparts, const int *flags,
+hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int *nparts, const int *flags,
                    hipStream_t st) {
     if (M.n == 0 || k == 0) return hipSuccess;
     if (k > 128) return hipErrorInvalidValue;
     return spmm_dispatch<T, 0, 2>(M, nullptr, nullptr, nullptr, p, ld, k, q, ld, p, ld, part, nparts, flags, st);
 }
-template hipError_t cg_spmm<double>(const DevCsr<double> &, const double *, double *, int64_t, int, double *, int,
+template hipError_t cg_spmm<double>(const DevCsr<double> &, const double *, double *, int64_t, int, double *, int *,
                                     const int *, hipStream_t);
-template hipError_t cg_spmm<float>(const DevCsr<float> &, const float *, float *, int64_t, int, float *, int,
+template hipError_t cg_spmm<float>(const DevCsr<float> &, const float *, float *, int64_t, int, float *, int *,
                                    const int *, hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -254,8 +627,8 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t n, int k, const double 
                                                  T *__restrict__ part, int nparts, int64_t rows_per) {
     constexpr int NG = 256 / G;
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
-    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r0 = (int64_t)chunk * rows_per, r1 = min(n, r0 + rows_per);
+    const int chunk = blockIdx.x;
+    const RowWalk rw = row_walk(n, NG);
     T acc[CT];
     double sc[CT];
 #pragma unroll
@@ -264,7 +637,9 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t n, int k, const double 
         const int c = lig + G * t;
         sc[t] = (c < k && rscale != nullptr) ? rscale[c] : 1.0;
     }
-    for (int64_t row = r0 + grp; row < r1; row += NG) {
+    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int64_t row = base + grp;
+        if (row >= rw.end) break;
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const int c = lig + G * t;
@@ -284,73 +659,86 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t n, int k, const double 
         if (c >= k) continue;
         T s = T(0);
         for (int g = 0; g < NG; ++g) s += sh[g][c];
-        part[(size_t)c * nparts + chunk] = s;
+        part[(size_t)c * gridDim.x + chunk] = s;
     }
 }
 
-template <typename T, int G, int CT>
-__global__ __launch_bounds__(256) void k_cg_update_r(int64_t n, int k, const T *__restrict__ q,
-                                                     T *__restrict__ r, int64_t ld, T *__restrict__ part,
-                                                     int nparts, int64_t rows_per, CgState<T> cs) {
+
+
+// Vector forms of the two CG update passes (16-byte accesses; same layout
+// conditions as k_spmmv).
+template <typename T, int G, int V>
+__global__ __launch_bounds__(256) void k_cg_update_r_v(int64_t n, int k, const T *__restrict__ q,
+                                                       T *__restrict__ r, int64_t ld, T *__restrict__ part,
+                                                       int nparts, int64_t rows_per, CgState<T> cs) {
     if (cs.flags[1] == 0) return;
     constexpr int NG = 256 / G;
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
-    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r0 = (int64_t)chunk * rows_per, r1 = min(n, r0 + rows_per);
-    T acc[CT], al[CT];
+    const int chunk = blockIdx.x;
+    const RowWalk rw = row_walk(n, NG);
+    const int c0 = lig * V;
+    const bool on = c0 < k;
+    T acc[V], al[V];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-        acc[t] = T(0);
-        const int c = lig + G * t;
-        al[t] = (c < k) ? cs.alpha[c] : T(0);
+    for (int v = 0; v < V; ++v) {
+        acc[v] = T(0);
+        al[v] = (c0 + v < k) ? cs.alpha[c0 + v] : T(0);
     }
-    for (int64_t row = r0 + grp; row < r1; row += NG) {
+    if (on) {
+        for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int64_t row = base + grp;
+        if (row >= rw.end) break;
+            const Vec<T, V> qv = vld<T, V>(q + row * ld + c0);
+            Vec<T, V> rv = vld<T, V>(r + row * ld + c0);
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            const int c = lig + G * t;
-            if (c >= k) continue;
-            const T v = fma(-al[t], q[row * ld + c], r[row * ld + c]);
-            r[row * ld + c] = v;
-            acc[t] = fma(v, v, acc[t]);
+            for (int v = 0; v < V; ++v) {
+                rv.v[v] = fma(-al[v], qv.v[v], rv.v[v]);
+                if (c0 + v < k) acc[v] = fma(rv.v[v], rv.v[v], acc[v]);
+            }
+            vst<T, V>(r + row * ld + c0, rv);
         }
     }
-    __shared__ T sh[NG][G * CT];
+    __shared__ T sh[NG][G * V];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) sh[grp][lig + G * t] = acc[t];
+    for (int v = 0; v < V; ++v) sh[grp][c0 + v] = acc[v];
     __syncthreads();
-    for (int c = tid; c < G * CT; c += 256) {
+    for (int c = tid; c < G * V; c += 256) {
         if (c >= k) continue;
         T s = T(0);
         for (int g = 0; g < NG; ++g) s += sh[g][c];
-        part[(size_t)c * nparts + chunk] = s;
+        part[(size_t)c * gridDim.x + chunk] = s;
     }
 }
 
-template <typename T, int G, int CT>
-__global__ __launch_bounds__(256) void k_cg_update_xp(int64_t n, int k, T *__restrict__ x, T *__restrict__ p,
-                                                      const T *__restrict__ r, int64_t ld, int64_t rows_per,
-                                                      CgState<T> cs) {
+template <typename T, int G, int V>
+__global__ __launch_bounds__(256) void k_cg_update_xp_v(int64_t n, int k, T *__restrict__ x, T *__restrict__ p,
+                                                        const T *__restrict__ r, int64_t ld, int64_t rows_per,
+                                                        CgState<T> cs) {
     if (cs.flags[1] == 0) return;
     constexpr int NG = 256 / G;
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
-    const int chunk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r0 = (int64_t)chunk * rows_per, r1 = min(n, r0 + rows_per);
-    T al[CT], be[CT];
+    const RowWalk rw = row_walk(n, NG);
+    const int c0 = lig * V;
+    if (c0 >= k) return;
+    T al[V], be[V];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-        const int c = lig + G * t;
-        al[t] = (c < k) ? cs.alpha[c] : T(0);
-        be[t] = (c < k) ? cs.beta[c] : T(0);
+    for (int v = 0; v < V; ++v) {
+        al[v] = (c0 + v < k) ? cs.alpha[c0 + v] : T(0);
+        be[v] = (c0 + v < k) ? cs.beta[c0 + v] : T(0);
     }
-    for (int64_t row = r0 + grp; row < r1; row += NG) {
+    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
+        const int64_t row = base + grp;
+        if (row >= rw.end) break;
+        const Vec<T, V> pv = vld<T, V>(p + row * ld + c0);
+        const Vec<T, V> rv = vld<T, V>(r + row * ld + c0);
+        Vec<T, V> xv = vld<T, V>(x + row * ld + c0), pn;
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            const int c = lig + G * t;
-            if (c >= k) continue;
-            const T pv = p[row * ld + c];
-            x[row * ld + c] = fma(al[t], pv, x[row * ld + c]);
-            p[row * ld + c] = fma(be[t], pv, r[row * ld + c]);
+        for (int v = 0; v < V; ++v) {
+            xv.v[v] = fma(al[v], pv.v[v], xv.v[v]);
+            pn.v[v] = fma(be[v], pv.v[v], rv.v[v]);
         }
+        vst<T, V>(x + row * ld + c0, xv);
+        vst<T, V>(p + row * ld + c0, pn);
     }
 }
 
@@ -438,22 +826,32 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const T *__restrict__ part, in
     }
 }
 
-#define GCGE_ROW_LAUNCH(KERNEL, T, k, ...)                                                              \
-    do {                                                                                               \
-        if ((k) <= 16) hipLaunchKernelGGL((KERNEL<T, 16, 1>), grid, block, 0, st, __VA_ARGS__);        \
-        else if ((k) <= 32) hipLaunchKernelGGL((KERNEL<T, 32, 1>), grid, block, 0, st, __VA_ARGS__);   \
-        else if ((k) <= 64) hipLaunchKernelGGL((KERNEL<T, 64, 1>), grid, block, 0, st, __VA_ARGS__);   \
-        else hipLaunchKernelGGL((KERNEL<T, 64, 2>), grid, block, 0, st, __VA_ARGS__);                  \
+// Launch a row kernel instance with its resident grid; the grid size is
+// stored in *np_out (the number of partials per column) when np_out != nullptr.
+#define GCGE_ROW_GO(INST, units, np_out, ...)                                              \
+    do {                                                                                   \
+        const int g_ = resident_grid((const void *)INST, (units));                         \
+        if (np_out) *(np_out) = g_;                                                        \
+        hipLaunchKernelGGL(INST, dim3(g_), dim3(256), 0, st, __VA_ARGS__);                 \
     } while (0)
 
 template <typename T>
 hipError_t cg_init(const double *R, int64_t ldr, const double *rscale, int k, int64_t n, T *r, T *p, T *x,
-                   int64_t ld, T *part, int nparts, CgState<T> cs, hipStream_t st) {
+                   int64_t ld, T *part, int *nparts, CgState<T> cs, hipStream_t st) {
     (void)cs;
     if (k > 128) return hipErrorInvalidValue;
-    dim3 grid(nparts), block(256);
-    const int64_t rp = rows_per_chunk(n, nparts);
-    GCGE_ROW_LAUNCH(k_cg_init, T, k, n, k, R, ldr, rscale, r, p, x, ld, part, nparts, rp);
+    const int G = k <= 16 ? 16 : k <= 32 ? 32 : 64, CT = k <= 64 ? 1 : 2;
+    const int64_t units = (n + 256 / G - 1) / (256 / G);
+    int g = 0;
+#define GCGE_CGI(Gv, CTv)                                                                       \
+    if (G == Gv && CT == CTv) {                                                                 \
+        g = resident_grid((const void *)k_cg_init<T, Gv, CTv>, units);                          \
+        hipLaunchKernelGGL((k_cg_init<T, Gv, CTv>), dim3(g), dim3(256), 0, st, n, k, R, ldr, rscale, r, p, x, \
+                           ld, part, g, (int64_t)0);                                            \
+    }
+    GCGE_CGI(16, 1) else GCGE_CGI(32, 1) else GCGE_CGI(64, 1) else GCGE_CGI(64, 2)
+#undef GCGE_CGI
+    *nparts = g;
     return hipGetLastError();
 }
 
@@ -470,13 +868,28 @@ hipError_t cg_alpha(const T *part, int nparts, int k, CgState<T> cs, hipStream_t
 }
 
 template <typename T>
-hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, int nparts, CgState<T> cs,
+static inline bool cg_vec_ok(int k, int64_t ld, const T *a, const T *b, const T *c) {
+    constexpr int V = 16 / sizeof(T);
+    const int kp = (k + V - 1) / V * V;
+    return ld % V == 0 && kp <= ld && kp <= 64 * V && aligned16(a) && aligned16(b) && aligned16(c);
+}
+
+template <typename T>
+hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, int *nparts, CgState<T> cs,
                        hipStream_t st) {
     if (k > 128) return hipErrorInvalidValue;
-    dim3 grid(nparts), block(256);
-    const int64_t rp = rows_per_chunk(n, nparts);
-    GCGE_ROW_LAUNCH(k_cg_update_r, T, k, n, k, q, r, ld, part, nparts, rp, cs);
-    return hipGetLastError();
+    constexpr int V = 16 / sizeof(T);
+    if (cg_vec_ok<T>(k, ld, q, r, r)) {
+        const int lanes = (k + V - 1) / V;
+        const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
+        const int64_t units = (n + 256 / G - 1) / (256 / G);
+#define GCGE_UR(Gv) \
+    if (G == Gv) { GCGE_ROW_GO((k_cg_update_r_v<T, Gv, V>), units, nparts, n, k, q, r, ld, part, 0, (int64_t)0, cs); }
+        GCGE_UR(4) else GCGE_UR(8) else GCGE_UR(16) else GCGE_UR(32) else GCGE_UR(64)
+#undef GCGE_UR
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -489,19 +902,27 @@ hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> 
 template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st) {
     if (k > 128) return hipErrorInvalidValue;
-    const int nparts = row_chunks(n, k);
-    dim3 grid(nparts), block(256);
-    const int64_t rp = rows_per_chunk(n, nparts);
-    GCGE_ROW_LAUNCH(k_cg_update_xp, T, k, n, k, x, p, r, ld, rp, cs);
-    return hipGetLastError();
+    constexpr int V = 16 / sizeof(T);
+    if (cg_vec_ok<T>(k, ld, x, p, r)) {
+        const int lanes = (k + V - 1) / V;
+        const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
+        const int64_t units = (n + 256 / G - 1) / (256 / G);
+        int *none = nullptr;
+#define GCGE_UX(Gv) \
+    if (G == Gv) { GCGE_ROW_GO((k_cg_update_xp_v<T, Gv, V>), units, none, n, k, x, p, r, ld, (int64_t)0, cs); }
+        GCGE_UX(4) else GCGE_UX(8) else GCGE_UX(16) else GCGE_UX(32) else GCGE_UX(64)
+#undef GCGE_UX
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 #define GCGE_CG_INST(T)                                                                                          \
     template hipError_t cg_init<T>(const double *, int64_t, const double *, int, int64_t, T *, T *, T *, int64_t, \
-                                   T *, int, CgState<T>, hipStream_t);                                            \
+                                   T *, int *, CgState<T>, hipStream_t);                                          \
     template hipError_t cg_init_finish<T>(const T *, int, int, CgState<T>, hipStream_t);                          \
     template hipError_t cg_alpha<T>(const T *, int, int, CgState<T>, hipStream_t);                                \
-    template hipError_t cg_update_r<T>(int64_t, int, const T *, T *, int64_t, T *, int, CgState<T>, hipStream_t); \
+    template hipError_t cg_update_r<T>(int64_t, int, const T *, T *, int64_t, T *, int *, CgState<T>, hipStream_t); \
     template hipError_t cg_beta<T>(const T *, int, int, double, CgState<T>, hipStream_t);                         \
     template hipError_t cg_update_xp<T>(int64_t, int, T *, T *, const T *, int64_t, CgState<T>, hipStream_t);
 GCGE_CG_INST(double)
@@ -566,21 +987,32 @@ __global__ __launch_bounds__(256) void k_gram(GramParams P) {
         yc[b] = yt * TN + b * 16 + li;
         yv[b] = yc[b] < P.k;
     }
-    for (int64_t rb = r0 + wave * 4; rb < r1; rb += 16) {
+    // operands of the next group of rows are requested before the MFMAs of
+    // the current group (register double buffering)
+    double av[MB], bv[NB], an[MB], bn[NB];
+    auto load = [&](int64_t rb, double *ao, double *bo) {
         const int64_t row = rb + lk;
         const bool rv = row < r1;
         const double *xr = tl.xp + row * tl.ldx;
         const double *yr = P.Y + row * P.ldy;
         const double dw = (P.d != nullptr && rv) ? P.d[row] : 1.0;
-        double av[MB], bv[NB];
 #pragma unroll
-        for (int a = 0; a < MB; ++a) av[a] = (rv && xv[a]) ? xr[xc[a]] : 0.0;
+        for (int a = 0; a < MB; ++a) ao[a] = (rv && xv[a]) ? xr[xc[a]] : 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = (rv && yv[b]) ? yr[yc[b]] * dw : 0.0;
+        for (int b = 0; b < NB; ++b) bo[b] = (rv && yv[b]) ? yr[yc[b]] * dw : 0.0;
+    };
+    int64_t rb = r0 + wave * 4;
+    load(rb, av, bv);
+    for (; rb < r1; rb += 16) {
+        load(rb + 16, an, bn);
 #pragma unroll
         for (int a = 0; a < MB; ++a)
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < MB; ++a) av[a] = an[a];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bv[b] = bn[b];
     }
     __shared__ double sh[TM * TN];
     for (int w = 0; w < 4; ++w) {
@@ -618,14 +1050,113 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramParams P, double *C, in
     }
 }
 
+// Large block inner products: a 64 x 64 tile of C per work-group over one
+// chunk of rows, 4 waves of 32 x 32.  Rows are staged through LDS 32 at a
+// time (X strip and the d-weighted Y strip); the next 32 rows are loaded into
+// registers while the MFMAs consume the current ones.  Each work-group writes
+// its partial tile; k_gram_reduce_lds sums the partials in chunk order.
+template <bool HAS_D>
+__global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
+    constexpr int T = 64, KR = 32;
+    __shared__ double Xs[KR][T];
+    __shared__ double Ys[KR][T];
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int per_chunk = P.ntile * P.nyt;
+    const int chunk = lid / per_chunk, rem = lid % per_chunk;
+    const int ti = rem / P.nyt, yt = rem % P.nyt;
+    const GTile tl = P.t[ti];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
+    const int wr = wave / 2, wc = wave % 2;
+    const int64_t r0 = (int64_t)chunk * P.rows_per, r1 = min(P.n, r0 + P.rows_per);
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    // staging: thread t holds column t % 64 of rows t / 64 + 4 q (q = 0..7), so
+    // each load instruction of a wave reads 64 consecutive doubles of one row.
+    // Addresses are clamped to valid elements and the values masked, so the
+    // loads carry no branches.
+    const int lc = tid % 64, lr = tid / 64;
+    const bool xcv = lc < tl.ncol, ycv = yt * T + lc < P.k;
+    const double *xbase = tl.xp + tl.xcol0 + (xcv ? lc : 0);
+    const double *ybase = P.Y + yt * T + (ycv ? lc : 0);
+    double xr[8], yr[8];
+    auto load = [&](int64_t rb) {
+        double xv[8], yv[8], dv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t row = min(rb + lr + 4 * q, r1 - 1);
+            xv[q] = xbase[row * tl.ldx];
+            yv[q] = ybase[row * P.ldy];
+            dv[q] = HAS_D ? P.d[row] : 1.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool rv = rb + lr + 4 * q < r1;
+            xr[q] = (rv && xcv) ? xv[q] : 0.0;
+            yr[q] = (rv && ycv) ? yv[q] * dv[q] : 0.0;
+        }
+    };
+    int64_t rb = r0;
+    if (rb < r1) load(rb);
+    for (; rb < r1; rb += KR) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            Xs[lr + 4 * q][lc] = xr[q];
+            Ys[lr + 4 * q][lc] = yr[q];
+        }
+        __syncthreads();
+        load(rb + KR);   // past the chunk end: clamped addresses, masked to zero
+#pragma unroll
+        for (int ks = 0; ks < KR; ks += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = Xs[ks + lk][wr * 32 + a * 16 + li];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Ys[ks + lk][wc * 32 + b * 16 + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double *dst = P.part + ((size_t)(ti * P.nyt + yt) * P.nchunk + chunk) * (T * T);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = wr * 32 + a * 16 + lk + 4 * r, j = wc * 32 + b * 16 + li;
+                dst[i * T + j] = acc[a][b][r];
+            }
+}
+
+// C tile elements summed over the chunks in chunk order; 16 work-groups per tile.
+__global__ __launch_bounds__(256) void k_gram_reduce_lds(GramParams P, double *C, int64_t ldc) {
+    constexpr int T = 64;
+    const int tp = blockIdx.x / 16, e = (blockIdx.x % 16) * 256 + threadIdx.x;
+    const int ti = tp / P.nyt, yt = tp % P.nyt;
+    const GTile tl = P.t[ti];
+    const int i = e / T, j = e % T, cj = yt * T + j;
+    if (i >= tl.ncol || cj >= P.k) return;
+    const double *src = P.part + (size_t)tp * P.nchunk * (T * T) + e;
+    double s = 0.0;
+    for (int c = 0; c < P.nchunk; ++c) s += src[(size_t)c * (T * T)];
+    C[(int64_t)(tl.crow0 + i) * ldc + cj] = s;
+}
+
 hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
                 int64_t ldc, Workspace &ws, hipStream_t st) {
     const int m = X.total();
     if (m == 0 || k == 0) return hipSuccess;
     int MB, NB;
+    const bool lds = !(m <= 32 && k <= 32);
     if (m <= 16 && k <= 16) { MB = 1; NB = 1; }
     else if (m <= 32 && k <= 32) { MB = 2; NB = 2; }
-    else if (k <= 16) { MB = 4; NB = 1; }
     else { MB = 4; NB = 4; }
     const int TM = 16 * MB, TN = 16 * NB;
     GramParams P;
@@ -645,10 +1176,12 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     P.nyt = (k + TN - 1) / TN;
     P.d = d;
     const int tiles = P.ntile * P.nyt;
-    int nchunk = std::max(1, 2048 / tiles);
+    // one residency wave of work-groups for the large-tile kernel
+    const int cap = lds ? resident_grid((const void *)k_gram_lds<false>, 1 << 30) : 2048;
+    int nchunk = std::max(1, cap / tiles);
     nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (n + 255) / 256));
     int64_t rp = (n + nchunk - 1) / nchunk;
-    rp = (rp + 15) / 16 * 16;
+    rp = (rp + 31) / 32 * 32;
     nchunk = (int)((n + rp - 1) / rp);
     P.nchunk = nchunk;
     P.rows_per = rp;
@@ -656,6 +1189,12 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     if (e != hipSuccess) return e;
     P.part = ws.part;
     dim3 grid(tiles * nchunk), block(256);
+    if (lds) {
+        if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, block, 0, st, P);
+        else hipLaunchKernelGGL(k_gram_lds<false>, grid, block, 0, st, P);
+        hipLaunchKernelGGL(k_gram_reduce_lds, dim3(tiles * 16), block, 0, st, P, C, ldc);
+        return hipGetLastError();
+    }
 #define GCGE_GRAM(MBv, NBv)                                                                     \
     if (MB == MBv && NB == NBv) {                                                               \
         hipLaunchKernelGGL((k_gram<MBv, NBv>), grid, block, 0, st, P);                          \
@@ -663,8 +1202,6 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     }
     GCGE_GRAM(1, 1)
     GCGE_GRAM(2, 2)
-    GCGE_GRAM(4, 1)
-    GCGE_GRAM(4, 4)
 #undef GCGE_GRAM
     return hipGetLastError();
 }
@@ -688,8 +1225,13 @@ struct GemmParams {
     int nct;
 };
 
+template <int BN>
 __global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
-    constexpr int BM = 64, BN = 64, BK = 16;
+    // BM x BN output tile per work-group, 4 waves as 2 x 2 of (BM/2) x (BN/2);
+    // K walked in chunks of BK columns across the X segments.  The next
+    // chunk's global loads are held in registers while the MFMAs consume the
+    // current chunk from LDS.
+    constexpr int BM = 128, BK = 16, MB = BM / 32, NB = BN / 32, SPT = BK * BN / 256;
     __shared__ double Vt[BM][BK + 1];
     __shared__ double St[BK][BN];
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -698,62 +1240,91 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
     const int col0 = ct * BN;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
     const int wr = wave / 2, wc = wave % 2;
-    d4 acc[2][2];
+    d4 acc[MB][NB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int sgi = 0; sgi < P.nseg; ++sgi) {
+        for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    // staging registers, lane-contiguous: V column tid % BK of rows tid / BK +
+    // 16 q; S column tid % BN of rows tid / BN + (256 / BN) q
+    constexpr int SRS = 256 / BN;
+    const int vc = tid % BK, vr = tid / BK;
+    const int sc = tid % BN, sr = tid / BN;
+    double vreg[8], sreg[SPT];
+    // clamped addresses, masked values: no branches around the loads
+    auto load_chunk = [&](int sgi, int kc) {
         const Seg sg = P.s[sgi];
-        const int soff = P.soff[sgi];
-        for (int kc = 0; kc < sg.ncol; kc += BK) {
-            {
-                const int r = tid / 4, c4 = (tid % 4) * 4;
-                const int64_t row = row0 + r;
-                const bool rv = row < P.n;
-                const double *src = sg.p + row * sg.ld + kc + c4;
+        const bool cv = kc + vc < sg.ncol;
+        const double *vb = sg.p + (cv ? kc + vc : 0);
+        double vv[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) Vt[r][c4 + q] = (rv && kc + c4 + q < sg.ncol) ? src[q] : 0.0;
-            }
-            {
-                const int kr = tid / 16, c4 = (tid % 16) * 4;
-                const int srow = kc + kr;
-                const bool sv = srow < sg.ncol;
-                const double *src = P.S + (int64_t)(soff + srow) * P.lds + col0 + c4;
+        for (int q = 0; q < 8; ++q) vv[q] = vb[min(row0 + vr + 16 * q, P.n - 1) * sg.ld];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) St[kr][c4 + q] = (sv && col0 + c4 + q < P.k) ? src[q] : 0.0;
-            }
-            __syncthreads();
+        for (int q = 0; q < 8; ++q) vreg[q] = (cv && row0 + vr + 16 * q < P.n) ? vv[q] : 0.0;
+        const bool scv = col0 + sc < P.k;
+        const double *sb = P.S + (int64_t)P.soff[sgi] * P.lds + (scv ? col0 + sc : 0);
+        double sv[SPT];
 #pragma unroll
-            for (int ks = 0; ks < BK; ks += 4) {
-                double av[2], bv[2];
+        for (int q = 0; q < SPT; ++q) sv[q] = sb[(int64_t)min(kc + sr + SRS * q, sg.ncol - 1) * P.lds];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = Vt[wr * 32 + a * 16 + li][ks + lk];
+        for (int q = 0; q < SPT; ++q) sreg[q] = (scv && kc + sr + SRS * q < sg.ncol) ? sv[q] : 0.0;
+    };
+    int sgi = 0, kc = 0;
+    bool have = P.nseg > 0;
+    if (have) load_chunk(0, 0);
+    while (have) {
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bv[b] = St[ks + lk][wc * 32 + b * 16 + li];
+        for (int q = 0; q < 8; ++q) Vt[vr + 16 * q][vc] = vreg[q];
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-            }
-            __syncthreads();
+        for (int q = 0; q < SPT; ++q) St[sr + SRS * q][sc] = sreg[q];
+        __syncthreads();
+        int nsgi = sgi, nkc = kc + BK;
+        if (nkc >= P.s[nsgi].ncol) {
+            ++nsgi;
+            nkc = 0;
         }
+        const bool nhave = nsgi < P.nseg;
+        if (nhave) load_chunk(nsgi, nkc);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            double av[MB], bv[NB];
+#pragma unroll
+            for (int a = 0; a < MB; ++a) av[a] = Vt[wr * (BM / 2) + a * 16 + li][ks + lk];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bv[b] = St[ks + lk][wc * (BN / 2) + b * 16 + li];
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+        sgi = nsgi;
+        kc = nkc;
+        have = nhave;
     }
+    // epilogue: the beta * Y reads use clamped addresses (no per-element
+    // branches); stores are masked
+    const bool addy = P.beta != 0.0;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NB; ++b) {
+            const int col = col0 + wc * (BN / 2) + b * 16 + li;
+            const int colc = min(col, P.k - 1);
+            double yv[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wr * 32 + a * 16 + lk + 4 * r;
-                const int col = col0 + wc * 32 + b * 16 + li;
-                if (row < P.n && col < P.k) {
-                    double v = P.alpha * acc[a][b][r];
-                    if (P.beta != 0.0) v = fma(P.beta, P.Y[row * P.ldy + col], v);
-                    P.Y[row * P.ldy + col] = v;
-                }
+                const int64_t row = min(row0 + wr * (BM / 2) + a * 16 + lk + 4 * r, P.n - 1);
+                yv[r] = addy ? P.Y[row * P.ldy + colc] : 0.0;
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wr * (BM / 2) + a * 16 + lk + 4 * r;
+                const double v = fma(P.beta, yv[r], P.alpha * acc[a][b][r]);
+                if (row < P.n && col < P.k) P.Y[row * P.ldy + col] = v;
+            }
+        }
 }
 
 hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
@@ -775,11 +1346,13 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
     P.beta = beta;
     P.Y = Y;
     P.ldy = ldy;
-    P.nct = (k + 63) / 64;
-    const int64_t nrt = (n + 63) / 64;
+    const int BN = (k <= 64) ? 64 : 128;
+    P.nct = (k + BN - 1) / BN;
+    const int64_t nrt = (n + 127) / 128;
     const int64_t nb = nrt * P.nct;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm, dim3((unsigned)nb), dim3(256), 0, st, P);
+    if (BN == 64) hipLaunchKernelGGL(k_gemm<64>, dim3((unsigned)nb), dim3(256), 0, st, P);
+    else hipLaunchKernelGGL(k_gemm<128>, dim3((unsigned)nb), dim3(256), 0, st, P);
     return hipGetLastError();
 }
 

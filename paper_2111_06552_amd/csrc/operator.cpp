@@ -237,7 +237,7 @@ hipError_t bop_apply(const BOp &B, int64_t n, const double *X, int64_t ldx, int 
     for (int c0 = 0; c0 < k; c0 += 128) {
         const int kk = std::min(128, k - c0);
         GCGE_TRY(spmm<double>(B.csr, nullptr, nullptr, nullptr, 0, 0, X + c0, ldx, kk, Y + c0, ldy, nullptr, 0,
-                              nullptr, 0, st));
+                              nullptr, nullptr, st));
     }
     return hipSuccess;
 }
@@ -247,7 +247,7 @@ hipError_t Operator::apply_b(const double *X, int64_t ldx, int k, double *Y, int
 }
 
 hipError_t Operator::residual(const double *X, int64_t ldx, int k, const double *sigma, double *R, int64_t ldr,
-                              double *part, int nparts, hipStream_t st) const {
+                              double *part, int *nparts, hipStream_t st) const {
     DevCsr<double> Ac = A_csr();
     if (bkind == GCGE_B_CSR)
         return spmm<double>(Ac, b, nullptr, sigma, 2, 1, X, ldx, k, R, ldr, nullptr, 0, part, nparts, st);

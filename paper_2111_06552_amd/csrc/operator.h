@@ -61,9 +61,10 @@ struct Operator {
     hipError_t shifted(double theta, double *m, float *m32, hipStream_t st) const;
     // Y = B X
     hipError_t apply_b(const double *X, int64_t ldx, int k, double *Y, int64_t ldy, hipStream_t st) const;
-    // R = A X - B X diag(sigma) with partial sums of r^2 and (Bx)^2 (sigma device).
+    // R = A X - B X diag(sigma) with partial sums of r^2 and (Bx)^2 (sigma device);
+    // *nparts receives the number of partials per column.
     hipError_t residual(const double *X, int64_t ldx, int k, const double *sigma, double *R, int64_t ldr,
-                        double *part, int nparts, hipStream_t st) const;
+                        double *part, int *nparts, hipStream_t st) const;
 };
 
 // Y = B X for a B operator.

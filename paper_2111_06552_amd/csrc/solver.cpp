@@ -118,22 +118,22 @@ struct CgRunner {
 
     int run(const DevCsr<T> &M, const double *R, int64_t ldr, const double *rscale, int k, int maxit,
             double rel_tol, T *x, T *r, T *p, T *q, int64_t ld, CgState<T> cs, int64_t *total_its) {
-        const int nparts = row_chunks(n, k);
-        hipError_t e = ws.ensure_part(sizeof(double) * (size_t)k * nparts + 256);
+        hipError_t e = ws.ensure_part(sizeof(double) * (size_t)k * max_row_parts() + 256);
         if (e != hipSuccess) return fail(e, "workspace");
         T *part = (T *)ws.part;
-        e = cg_init<T>(R, ldr, rscale, k, n, r, p, x, ld, part, nparts, cs, st);
+        int nparts = 0;
+        e = cg_init<T>(R, ldr, rscale, k, n, r, p, x, ld, part, &nparts, cs, st);
         if (e == hipSuccess) e = cg_init_finish<T>(part, nparts, k, cs, st);
         if (e != hipSuccess) return fail(e, "cg init");
         bool pending = false;
         int it = 0;
         for (; it < maxit; ++it) {
             int pb = prof ? prof->begin(st) : -1;
-            e = cg_spmm<T>(M, p, q, ld, k, part, nparts, cs.flags, st);
+            e = cg_spmm<T>(M, p, q, ld, k, part, &nparts, cs.flags, st);
             if (prof) prof->end(0, pb, k, st);
             if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
             pb = prof ? prof->begin(st) : -1;
-            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, nparts, cs, st);
+            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, cs, st);
             if (prof) prof->end(3, pb, k, st);
             if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
             pb = prof ? prof->begin(st) : -1;
@@ -305,13 +305,13 @@ int gcge_handle_s::do_residual(const double *X, int64_t ldx, int k, const double
     rn.assign(k, 0.0);
     bn.assign(k, 0.0);
     if (k == 0) return GCGE_OK;
-    const int nparts = row_chunks(op.n, k);
-    hipError_t e = ws.ensure_part(sizeof(double) * 2 * (size_t)k * nparts + 256);
+    int nparts = 0;
+    hipError_t e = ws.ensure_part(sizeof(double) * 2 * (size_t)k * max_row_parts() + 256);
     if (e == hipSuccess) e = ws.ensure_colvec(sizeof(double) * (3 * k + 64));
     if (e != hipSuccess) return hipfail(e, "workspace");
     double *sig = ws.colvec, *out = ws.colvec + k + 16;
     e = stg.upload(sig, lam, sizeof(double) * k);
-    if (e == hipSuccess) e = op.residual(X, ldx, k, sig, R, ldr, ws.part, nparts, st);
+    if (e == hipSuccess) e = op.residual(X, ldx, k, sig, R, ldr, ws.part, &nparts, st);
     if (e == hipSuccess) e = colsum<double>(ws.part, nparts, 2 * k, out, st);
     std::vector<double> h(2 * k);
     if (e == hipSuccess) e = stg.download(h.data(), out, sizeof(double) * 2 * k);
@@ -420,7 +420,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     for (int c0 = 0; c0 < k0; c0 += 128) {
         const int kk = std::min(128, k0 - c0);
         e = spmm<double>(op.A_csr(), nullptr, nullptr, nullptr, 0, 0, Xb[0] + c0, ldX, kk, Xb[1] + c0, ldX, nullptr,
-                         0, nullptr, 0, st);
+                         0, nullptr, nullptr, st);
         if (e != hipSuccess) return hipfail(e, "A X");
     }
     S.spmm_columns += k0;
@@ -548,8 +548,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         // ---------------- STEP 3: Rayleigh-Ritz with the structured Abar
         auto t3 = Clock::now();
         if (nw > 0) {
-            e = spmm<double>(op.A_csr(), nullptr, nullptr, nullptr, 0, 0, Wb, ldB, nw, AWb, ldB, nullptr, 0, nullptr,
-                             0, st);
+            e = spmm<double>(op.A_csr(), nullptr, nullptr, nullptr, 0, 0, Wb, ldB, nw, AWb, ldB, nullptr, 0, nullptr, nullptr, st);
             if (e != hipSuccess) return hipfail(e, "A W");
             S.spmm_columns += nw;
         }
@@ -887,7 +886,7 @@ extern "C" int gcge_spmm(const gcge_csr *A, const double *X, int64_t ldx, int k,
     for (int c0 = 0; c0 < k; c0 += 128) {
         const int kk = std::min(128, k - c0);
         hipError_t e = spmm<double>(to_dev(A), nullptr, nullptr, nullptr, 0, 0, X + c0, ldx, kk, Y + c0, ldy, nullptr,
-                                    0, nullptr, 0, st);
+                                    0, nullptr, nullptr, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm");
     }
     return GCGE_OK;
@@ -902,7 +901,7 @@ extern "C" int gcge_spmm_f32(int64_t n, const int32_t *rowptr, const int32_t *co
     for (int c0 = 0; c0 < k; c0 += 128) {
         const int kk = std::min(128, k - c0);
         hipError_t e = spmm<float>(A, nullptr, nullptr, nullptr, 0, 0, X + c0, ldx, kk, Y + c0, ldy, nullptr, 0,
-                                   nullptr, 0, st);
+                                   nullptr, nullptr, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm_f32");
     }
     return GCGE_OK;
@@ -934,13 +933,13 @@ static int shifted_or_residual(const gcge_csr *A, int b_kind, const void *B, con
     hipError_t e = hipSuccess;
     for (int c0 = 0; c0 < k && e == hipSuccess; c0 += 128) {
         const int kk = std::min(128, k - c0);
-        const int nparts = row_chunks(op.n, kk);
-        e = C.ws.ensure_part(sizeof(double) * 2 * (size_t)kk * nparts + 256);
+        int nparts = 0;
+        e = C.ws.ensure_part(sizeof(double) * 2 * (size_t)kk * max_row_parts() + 256);
         if (e == hipSuccess) e = C.ws.ensure_colvec(sizeof(double) * (3 * kk + 64));
         if (e != hipSuccess) break;
         double *sig = C.ws.colvec, *out = C.ws.colvec + kk + 16;
         e = C.stg.upload(sig, sigma + c0, sizeof(double) * kk);
-        if (e == hipSuccess) e = op.residual(X + c0, ldx, kk, sig, Y + c0, ldy, C.ws.part, nparts, st);
+        if (e == hipSuccess) e = op.residual(X + c0, ldx, kk, sig, Y + c0, ldy, C.ws.part, &nparts, st);
         if (e == hipSuccess && rnorm) {
             std::vector<double> h(2 * kk);
             e = colsum<double>(C.ws.part, nparts, 2 * kk, out, st);
