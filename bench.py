@@ -35,34 +35,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def dominant_roofline(prof, n, nnz, s=8):
-    """Achieved rate of the kernel class with the largest device time.
+def row_kernel(base, s, k, tail=""):
+    """Name of the row-streaming kernel instance launched for k columns of
+    s-byte scalars (16-byte accesses: V = 16 / s scalars per lane, G lanes per row)."""
+    v = 16 // s
+    lanes = (k + v - 1) // v
+    g = next(x for x in (4, 8, 16, 32, 64) if lanes <= x)
+    return f"{base}<{'double' if s == 8 else 'float'}, {g}, {v}{tail}>"
 
-    CG SpMM (HBM bound), algorithmic bytes per launch with k columns:
-        nnz * (4 + s) + 4 (n + 1) + 2 n k s      (CSR once, p gathered once, q written once)
-    Rotation GEMM (MFMA bound), flops per launch: 2 n m k."""
-    name = max(prof, key=lambda c: prof[c]["ms"])
-    p = prof[name]
+
+def class_roofline(name, p, n, nnz, s=8, bs=None):
+    """Achieved rate of one kernel class from its HIP-event timings.
+
+    Algorithmic bytes per launch with k columns (s bytes per scalar):
+      CG SpMM        nnz (4 + s) + 4 (n + 1) + 2 n k s   (CSR once, p gathered once, q written once)
+      CG r update    3 n k s                              (q, r read; r written)
+      CG x, p update 5 n k s                              (x, p, r read; x, p written)
+    For the CG classes only the launches over a full block (k = bs columns, one
+    kernel instance) are used.  Flops per launch of the GEMMs and Grams with
+    m x k coefficient blocks: 2 n m k."""
     if p["launches"] == 0 or p["ms"] <= 0:
-        return None, name
+        return None
     avg_ms = p["ms"] / p["launches"]
-    if name == "cg_spmm":
-        total = p["launches"] * (nnz * (4 + s) + 4 * (n + 1)) + p["columns"] * 2 * n * s
-        per_launch = total / p["launches"]
+    k = p["columns"] / p["launches"]
+    launches = p["launches"]
+    if bs is not None and p.get("full_launches"):
+        avg_ms = p["full_ms"] / p["full_launches"]
+        k = bs
+        launches = p["full_launches"]
+    kr = round(k)
+    hbm = {"cg_spmm": lambda: (nnz * (4 + s) + 4 * (n + 1) + 2 * n * k * s,
+                               row_kernel("k_spmms", s, kr, ", 0, 2") + " (CG: q = (A - theta B) p with p.q)"),
+           "cg_update_r": lambda: (3 * n * k * s, row_kernel("k_cg_update_r_v", s, kr) + " (CG: r -= alpha q, r.r)"),
+           "cg_update_xp": lambda: (5 * n * k * s,
+                                    row_kernel("k_cg_update_xp_v", s, kr) + " (CG: x += alpha p, p = r + beta p)")}
+    if name in hbm:
+        per_launch, kern = hbm[name]()
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        return {"kernel": "k_spmm<double,64,1,0,2> (CG: q = (A - theta B) p, p.q)", "bound": "hbm",
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
-                "launches": p["launches"]}, name
-    if name == "rotation_gemm":
-        flops = 2.0 * n * p["columns"]
-        per_launch = flops / p["launches"]
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        return {"kernel": "k_gemm (Ritz rotation V_u xhat, P = V_u phat)", "bound": "mfma", "achieved": achieved,
-                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                "traffic": None, "algorithmic_flops_per_launch": per_launch, "avg_launch_ms": avg_ms,
-                "launches": p["launches"]}, name
-    return {"kernel": name, "avg_launch_ms": avg_ms, "launches": p["launches"]}, name
+        return {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": per_launch,
+                "avg_launch_ms": avg_ms, "launches": launches}
+    kern = {"rotation_gemm": "k_gemm (Ritz rotation V_u xhat)", "p_gemm": "k_gemm (P block V_u phat)",
+            "gram": "k_gram_lds + k_tile_reduce (Gram products)"}[name]
+    per_launch = 2.0 * n * k
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    return {"kernel": kern, "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+            "algorithmic_flops_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": p["launches"]}
+
+
+def dominant_roofline(prof, n, nnz, s=8, bs=None):
+    """Roofline entry of the kernel class with the largest summed device time."""
+    name = max(prof, key=lambda c: prof[c]["ms"])
+    return class_roofline(name, prof[name], n, nnz, s, bs), name
+
+
+def sum_prof(stats):
+    """Per-class HIP-event totals over several solves."""
+    out = {}
+    for c in stats[0]["prof"]:
+        if c.startswith("unused"):
+            continue
+        out[c] = {f: sum(x["prof"][c][f] for x in stats) for f in stats[0]["prof"][c]}
+    return out
 
 
 def cpu_baseline(A, spmm_columns, budget_s):
@@ -91,6 +126,81 @@ def cpu_baseline(A, spmm_columns, budget_s):
                       f"excludes the orthogonalization and Rayleigh-Ritz work"}
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2111_06552_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic.json")
+
+
+def short_name(kernel_name):
+    """'void gcge::k_x<double, 32, 2>(long, ...)' -> 'k_x<double, 32, 2>'."""
+    n = kernel_name.split("(")[0]
+    for pre in ("void ", "gcge::"):
+        n = n.replace(pre, "")
+    return n.strip()
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def summarize_trace(d, top=30):
+    """Markdown table of a rocprofv3 --stats kernel summary (directory d)."""
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))[-1]
+    rows = list(csv.DictReader(open(f)))
+    lines = ["| kernel | calls | total ms | average us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {r['Percentage']} |")
+    return "\n".join(lines)
+
+
+def pmc_means(d, counter):
+    """Mean counter value per dispatch and kernel of a rocprofv3 --pmc run (directory d)."""
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[-1]
+    acc = {}
+    for r in csv.DictReader(open(f)):
+        if r["Counter_Name"] != counter:
+            continue
+        v = acc.setdefault(short_name(r["Kernel_Name"]), [0.0, 0])
+        v[0] += float(r["Counter_Value"])
+        v[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+    """HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch),
+    each scaled by what the counter reads for a plain streaming kernel that reads and
+    writes copy_bytes."""
+    cf = max(pmc_means(copy_fetch_dir, "FETCH_SIZE").values())
+    cw = max(pmc_means(copy_write_dir, "WRITE_SIZE").values())
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    fe, wr = pmc_means(fetch_dir, "FETCH_SIZE"), pmc_means(write_dir, "WRITE_SIZE")
+    out = {"kernels_hip_sha256": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_dispatch": {k: fe[k] * 1024.0 * f_scale + wr.get(k, 0.0) * 1024.0 * w_scale for k in fe},
+           "fetch_bytes_per_dispatch": {k: fe[k] * 1024.0 * f_scale for k in fe},
+           "write_bytes_per_dispatch": {k: wr[k] * 1024.0 * w_scale for k in wr}}
+    return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    there is none or the kernel source changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_hip_sha256") != kernel_source_hash():
+        return None
+    return t["bytes_per_dispatch"].get(short_name(kernel.split(" (")[0]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +211,22 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown table of a rocprofv3 --stats run")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                            "COPY_WRITE_DIR"),
+                    help="write the per-kernel HBM traffic of rocprofv3 --pmc runs to profiles/kernel_traffic.json")
+    ap.add_argument("--copy-bytes", type=float, default=float(2 ** 30),
+                    help="bytes read (and written) by each dispatch of the calibration copy")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_traffic:
+        t = summarize_traffic(*args.summarize_traffic, args.copy_bytes)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(t, f, indent=1, sort_keys=True)
+        print(json.dumps({k: t[k] for k in ("fetch_scale", "write_scale")}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU row "
               f"partition is a design, not built", file=sys.stderr)
@@ -160,10 +285,12 @@ def main():
     out["solve"]["step_ms"] = {k: round(v, 2) for k, v in st["time_ms"].items()}
     out["solve"]["times_s"] = [round(x, 4) for x in t64.tolist()]
     # roofline from every launch of the timed solves
-    prof = {c: {"ms": sum(x["prof"][c]["ms"] for x in s64), "launches": sum(x["prof"][c]["launches"] for x in s64),
-                "columns": sum(x["prof"][c]["columns"] for x in s64)} for c in s64[0]["prof"]}
-    roof, name = dominant_roofline(prof, A.n, A.nnz)
+    prof = sum_prof(s64)
+    roof, name = dominant_roofline(prof, A.n, A.nnz, bs=bs)
+    if roof is not None and roof.get("bound") == "hbm":
+        roof["traffic"] = measured_traffic(roof["kernel"])
     out["roofline"] = roof
+    out["kernel_rooflines"] = {c: class_roofline(c, prof[c], A.n, A.nnz, bs=bs) for c in prof}
     out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"] / args.steps, 2) for c in prof}
     if not args.no_mixed:
         tm, sm, lamm = run("mixed", args.steps, args.warmup)
@@ -172,13 +299,9 @@ def main():
                         "max_eig_rel_diff_vs_fp64": float(np.max(np.abs(lamm - lam64) / np.abs(lam64))),
                         "iterations": sm[-1]["iterations"], "cg_iterations": sm[-1]["cg_iterations"],
                         "max_rel_residual": sm[-1]["max_rel_residual"], "dtype": "f32 inner CG, f64 elsewhere"}
-        profm = {c: {"ms": sum(x["prof"][c]["ms"] for x in sm),
-                     "launches": sum(x["prof"][c]["launches"] for x in sm),
-                     "columns": sum(x["prof"][c]["columns"] for x in sm)} for c in sm[0]["prof"]}
-        if profm["cg_spmm"]["launches"]:
-            r32, _ = dominant_roofline({"cg_spmm": profm["cg_spmm"]}, A.n, A.nnz, s=4)
-            out["mixed"]["cg_spmm_gbs"] = r32["achieved"]
-            out["mixed"]["cg_spmm_frac"] = r32["frac"]
+        profm = sum_prof(sm)
+        out["mixed"]["kernel_rooflines"] = {c: class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs)
+                                            for c in ("cg_spmm", "cg_update_r", "cg_update_xp")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, int(st["spmm_columns"]), args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -86,12 +86,19 @@ typedef struct {
     double orth_error;       /* max |X^T B X - I| over the returned vectors               */
     /* With option "profile" = 1: device time (HIP events on the solver stream
      * around each launch) summed per kernel class, the number of launches and
-     * the summed column count of the launches.  Classes: 0 CG SpMM (q = (A -
-     * theta B) p with p.q), 1 Ritz rotation / P GEMM (V_u xhat, V_u phat),
-     * 2 Gram products, 3 CG vector updates. */
-    double prof_ms[4];
-    int64_t prof_launches[4];
-    int64_t prof_columns[4];
+     * the summed column count of the launches (for the GEMMs and Grams: the
+     * product of the two column counts).  Classes: 0 CG SpMM (q = (A - theta
+     * B) p with p.q), 1 CG residual update (r -= alpha q with r.r), 2 CG
+     * iterate and direction update (x += alpha p, p = r + beta p), 3 Ritz
+     * rotation (V_u xhat), 4 P block (V_u phat), 5 Gram products of the
+     * solver driver (initial and Rayleigh-Ritz); 6 and 7 are unused (zero). */
+    double prof_ms[8];
+    int64_t prof_launches[8];
+    int64_t prof_columns[8];
+    /* The part of classes 0-2 whose launches span a full block (block_size
+     * columns); entry 3 is unused (zero). */
+    double prof_full_ms[4];
+    int64_t prof_full_launches[4];
 } gcge_stats;
 
 /* ------------------------------------------------------------------ solver */

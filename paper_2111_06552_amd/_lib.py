@@ -18,7 +18,7 @@ GCGE_ERR_INTERNAL = -5
 B_IDENTITY, B_DIAG, B_CSR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
-PROF_NAMES = ["cg_spmm", "rotation_gemm", "gram", "cg_update"]
+PROF_NAMES = ["cg_spmm", "cg_update_r", "cg_update_xp", "rotation_gemm", "p_gemm", "gram", "unused6", "unused7"]
 STEP_NAMES = ["init", "step2_orth", "step3_rr", "step4_conv", "step5_p", "step6_cg", "final_check", "total"]
 
 # Every symbol declared in include/gcge.h.
@@ -46,15 +46,20 @@ class Stats(ctypes.Structure):
                 ("reserved0", ctypes.c_int32), ("cg_iterations", ctypes.c_int64),
                 ("spmm_columns", ctypes.c_int64), ("time_ms", ctypes.c_double * 8),
                 ("max_rel_residual", ctypes.c_double), ("orth_error", ctypes.c_double),
-                ("prof_ms", ctypes.c_double * 4), ("prof_launches", ctypes.c_int64 * 4),
-                ("prof_columns", ctypes.c_int64 * 4)]
+                ("prof_ms", ctypes.c_double * 8), ("prof_launches", ctypes.c_int64 * 8),
+                ("prof_columns", ctypes.c_int64 * 8), ("prof_full_ms", ctypes.c_double * 4),
+                ("prof_full_launches", ctypes.c_int64 * 4)]
 
     def as_dict(self):
-        skip = ("time_ms", "reserved0", "prof_ms", "prof_launches", "prof_columns")
+        skip = ("time_ms", "reserved0", "prof_ms", "prof_launches", "prof_columns", "prof_full_ms",
+                "prof_full_launches")
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in skip}
         d["time_ms"] = {name: self.time_ms[i] for i, name in enumerate(STEP_NAMES)}
         d["prof"] = {name: {"ms": self.prof_ms[i], "launches": self.prof_launches[i],
                             "columns": self.prof_columns[i]} for i, name in enumerate(PROF_NAMES)}
+        for i, name in enumerate(PROF_NAMES[:3]):
+            d["prof"][name]["full_ms"] = self.prof_full_ms[i]
+            d["prof"][name]["full_launches"] = self.prof_full_launches[i]
         return d
 
 

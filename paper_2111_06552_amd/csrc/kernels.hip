@@ -592,19 +592,50 @@ template hipError_t cg_spmm<float>(const DevCsr<float> &, const float *, float *
 // ---------------------------------------------------------------------------
 // fixed-order column sums of partials (one work-group, 16 waves)
 // ---------------------------------------------------------------------------
+// Wave w sums the partials of columns c = c0 + w + 16 i (i < 8, c < k) of the
+// layout part[c * nparts + p]: lane l accumulates p = l, l + 64, ... in
+// increasing order (four rows of partials of all eight columns in flight),
+// then the lanes are combined by wave_sum.  out[i] is valid in every lane.
 template <typename T>
-__device__ __forceinline__ T colsum_wave(const T *__restrict__ part, int nparts, int c, int lane) {
-    T s = T(0);
-    for (int p = lane; p < nparts; p += 64) s += part[(size_t)c * nparts + p];
-    return wave_sum(s);
+__device__ __forceinline__ void colsums_wave(const T *__restrict__ part, int nparts, int k, int c0, int w,
+                                             int lane, T out[8]) {
+    T s[8];
+    bool own[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        s[i] = T(0);
+        own[i] = c0 + w + 16 * i < k;
+    }
+    const T *base = part + (size_t)(c0 + w) * nparts;
+    int p = lane;
+    for (; p + 192 < nparts; p += 256) {
+        T v[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[u][i] = own[i] ? base[(size_t)16 * i * nparts + p + 64 * u] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s[i] += v[u][i];
+    }
+    for (; p < nparts; p += 64)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] += own[i] ? base[(size_t)16 * i * nparts + p] : T(0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = wave_sum(s[i]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_colsum(const T *__restrict__ part, int nparts, int k, double *out) {
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int c = w; c < k; c += 16) {
-        const T s = colsum_wave(part, nparts, c, lane);
-        if (lane == 0) out[c] = (double)s;
+    for (int c0 = 0; c0 < k; c0 += 128) {
+        T sums[8];
+        colsums_wave(part, nparts, k, c0, w, lane, sums);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (c0 + w + 16 * i < k) out[c0 + w + 16 * i] = (double)sums[i];
     }
 }
 
@@ -747,16 +778,22 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_cg_init_finish(const T *__restrict__ part, int nparts, int k,
                                                          CgState<T> cs) {
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int c = w; c < k; c += 16) {
-        const T s = colsum_wave(part, nparts, c, lane);
-        if (lane == 0) {
-            cs.rr[c] = s;
-            cs.rr0[c] = s;
-            cs.active[c] = (s > T(0)) ? 1 : 0;
-            cs.its[c] = 0;
-            cs.alpha[c] = T(0);
-            cs.beta[c] = T(0);
-        }
+    for (int c0 = 0; c0 < k; c0 += 128) {
+        T sums[8];
+        colsums_wave(part, nparts, k, c0, w, lane, sums);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = c0 + w + 16 * i;
+                if (c >= k) continue;
+                const T s = sums[i];
+                cs.rr[c] = s;
+                cs.rr0[c] = s;
+                cs.active[c] = (s > T(0)) ? 1 : 0;
+                cs.its[c] = 0;
+                cs.alpha[c] = T(0);
+                cs.beta[c] = T(0);
+            }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -774,20 +811,26 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const T *__restrict__ part, i
         return;
     }
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int c = w; c < k; c += 16) {
-        const T pq = colsum_wave(part, nparts, c, lane);
-        if (lane == 0) {
-            T al = T(0);
-            if (cs.active[c]) {
-                if (pq > T(0)) {
-                    al = cs.rr[c] / pq;
-                    cs.its[c] += 1;
-                } else {
-                    cs.active[c] = 0;   // p^T (A - theta B) p <= 0: freeze the column
+    for (int c0 = 0; c0 < k; c0 += 128) {
+        T sums[8];
+        colsums_wave(part, nparts, k, c0, w, lane, sums);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = c0 + w + 16 * i;
+                if (c >= k) continue;
+                const T pq = sums[i];
+                T al = T(0);
+                if (cs.active[c]) {
+                    if (pq > T(0)) {
+                        al = cs.rr[c] / pq;
+                        cs.its[c] += 1;
+                    } else {
+                        cs.active[c] = 0;   // p^T (A - theta B) p <= 0: freeze the column
+                    }
                 }
+                cs.alpha[c] = al;
             }
-            cs.alpha[c] = al;
-        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -806,17 +849,23 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const T *__restrict__ part, in
                                                   CgState<T> cs) {
     if (cs.flags[1] == 0) return;
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int c = w; c < k; c += 16) {
-        const T rrn = colsum_wave(part, nparts, c, lane);
-        if (lane == 0) {
-            T be = T(0);
-            if (cs.alpha[c] != T(0)) {
-                be = rrn / cs.rr[c];
-                cs.rr[c] = rrn;
-                if (rrn <= tol2 * cs.rr0[c]) cs.active[c] = 0;
+    for (int c0 = 0; c0 < k; c0 += 128) {
+        T sums[8];
+        colsums_wave(part, nparts, k, c0, w, lane, sums);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = c0 + w + 16 * i;
+                if (c >= k) continue;
+                const T rrn = sums[i];
+                T be = T(0);
+                if (cs.alpha[c] != T(0)) {
+                    be = rrn / cs.rr[c];
+                    cs.rr[c] = rrn;
+                    if (rrn <= tol2 * cs.rr0[c]) cs.active[c] = 0;
+                }
+                cs.beta[c] = be;
             }
-            cs.beta[c] = be;
-        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1033,28 +1082,47 @@ __global__ __launch_bounds__(256) void k_gram(GramParams P) {
     for (int e = threadIdx.x; e < TM * TN; e += 256) dst[e] = sh[e];
 }
 
-template <int MB, int NB>
-__global__ __launch_bounds__(256) void k_gram_reduce(GramParams P, double *C, int64_t ldc) {
-    constexpr int TM = 16 * MB, TN = 16 * NB;
-    const int tp = blockIdx.x;
+// Fixed-order sums of the per-chunk partial tiles: element e of tile tp is
+// the sum over c of part[(tp * nchunk + c) * TE + e].  A work-group of 16 waves
+// covers 64 consecutive elements; wave w sums the w-th of 16 contiguous chunk
+// ranges with 8 independent loads in flight, then the 16 range sums are added
+// in range order.  The order depends only on nchunk, so results are
+// reproducible.
+__global__ __launch_bounds__(1024) void k_tile_reduce(GramParams P, int TN, int TE, double *C, int64_t ldc) {
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int epb = (TE + 63) / 64;
+    const int tp = blockIdx.x / epb, e = (blockIdx.x % epb) * 64 + lane;
+    const int cs = (P.nchunk + 15) / 16;
+    const int c_lo = min(P.nchunk, w * cs), c_hi = min(P.nchunk, c_lo + cs);
+    const double *src = P.part + (size_t)tp * P.nchunk * TE + min(e, TE - 1);
+    double s = 0.0;
+    int c = c_lo;
+    for (; c + 8 <= c_hi; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(c + u) * TE];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < c_hi; ++c) s += src[(size_t)c * TE];
+    __shared__ double red[16][64];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || e >= TE) return;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += red[i][lane];
     const int ti = tp / P.nyt, yt = tp % P.nyt;
     const GTile tl = P.t[ti];
-    const double *src = P.part + (size_t)tp * P.nchunk * (TM * TN);
-    for (int e = threadIdx.x; e < TM * TN; e += 256) {
-        const int i = e / TN, j = e % TN;
-        const int cj = yt * TN + j;
-        if (i >= tl.ncol || cj >= P.k) continue;
-        double s = 0.0;
-        for (int c = 0; c < P.nchunk; ++c) s += src[(size_t)c * (TM * TN) + e];
-        C[(int64_t)(tl.crow0 + i) * ldc + cj] = s;
-    }
+    const int i = e / TN, j = e % TN, cj = yt * TN + j;
+    if (i < tl.ncol && cj < P.k) C[(int64_t)(tl.crow0 + i) * ldc + cj] = t;
 }
 
 // Large block inner products: a 64 x 64 tile of C per work-group over one
 // chunk of rows, 4 waves of 32 x 32.  Rows are staged through LDS 32 at a
 // time (X strip and the d-weighted Y strip); the next 32 rows are loaded into
 // registers while the MFMAs consume the current ones.  Each work-group writes
-// its partial tile; k_gram_reduce_lds sums the partials in chunk order.
+// its partial tile; k_tile_reduce sums the partials.
 template <bool HAS_D>
 __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
     constexpr int T = 64, KR = 32;
@@ -1135,20 +1203,6 @@ __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
             }
 }
 
-// C tile elements summed over the chunks in chunk order; 16 work-groups per tile.
-__global__ __launch_bounds__(256) void k_gram_reduce_lds(GramParams P, double *C, int64_t ldc) {
-    constexpr int T = 64;
-    const int tp = blockIdx.x / 16, e = (blockIdx.x % 16) * 256 + threadIdx.x;
-    const int ti = tp / P.nyt, yt = tp % P.nyt;
-    const GTile tl = P.t[ti];
-    const int i = e / T, j = e % T, cj = yt * T + j;
-    if (i >= tl.ncol || cj >= P.k) return;
-    const double *src = P.part + (size_t)tp * P.nchunk * (T * T) + e;
-    double s = 0.0;
-    for (int c = 0; c < P.nchunk; ++c) s += src[(size_t)c * (T * T)];
-    C[(int64_t)(tl.crow0 + i) * ldc + cj] = s;
-}
-
 hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
                 int64_t ldc, Workspace &ws, hipStream_t st) {
     const int m = X.total();
@@ -1192,13 +1246,13 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     if (lds) {
         if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, block, 0, st, P);
         else hipLaunchKernelGGL(k_gram_lds<false>, grid, block, 0, st, P);
-        hipLaunchKernelGGL(k_gram_reduce_lds, dim3(tiles * 16), block, 0, st, P, C, ldc);
+        hipLaunchKernelGGL(k_tile_reduce, dim3(tiles * (TM * TN / 64)), dim3(1024), 0, st, P, TN, TM * TN, C, ldc);
         return hipGetLastError();
     }
 #define GCGE_GRAM(MBv, NBv)                                                                     \
     if (MB == MBv && NB == NBv) {                                                               \
         hipLaunchKernelGGL((k_gram<MBv, NBv>), grid, block, 0, st, P);                          \
-        hipLaunchKernelGGL((k_gram_reduce<MBv, NBv>), dim3(tiles), block, 0, st, P, C, ldc);     \
+        hipLaunchKernelGGL(k_tile_reduce, dim3(tiles * (TM * TN / 64)), dim3(1024), 0, st, P, TN, TM * TN, C, ldc); \
     }
     GCGE_GRAM(1, 1)
     GCGE_GRAM(2, 2)

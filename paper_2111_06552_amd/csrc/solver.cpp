@@ -62,6 +62,7 @@ struct Buffers {
 // times are read once at the end of a solve.
 struct KProf {
     bool on = false;
+    int64_t full_cols = -1;   // CG launches over this many columns are also summed separately
     std::vector<hipEvent_t> pool;
     size_t next = 0;
     struct Mark {
@@ -92,6 +93,10 @@ struct KProf {
                 S.prof_ms[m.cls] += ms;
                 S.prof_launches[m.cls] += 1;
                 S.prof_columns[m.cls] += m.cols;
+                if (m.cls < 3 && m.cols == full_cols) {
+                    S.prof_full_ms[m.cls] += ms;
+                    S.prof_full_launches[m.cls] += 1;
+                }
             }
         }
         marks.clear();
@@ -134,11 +139,11 @@ struct CgRunner {
             if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
             pb = prof ? prof->begin(st) : -1;
             if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, cs, st);
-            if (prof) prof->end(3, pb, k, st);
+            if (prof) prof->end(1, pb, k, st);
             if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
             pb = prof ? prof->begin(st) : -1;
             if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, r, ld, cs, st);
-            if (prof) prof->end(3, pb, k, st);
+            if (prof) prof->end(2, pb, k, st);
             if (e != hipSuccess) return fail(e, "cg iteration");
             if (pinned_flag != nullptr && (it % 4) == 3) {
                 // non-blocking poll of the number of active columns
@@ -226,7 +231,7 @@ struct gcge_handle_s {
                     std::vector<double> &rn, std::vector<double> &bn);
     int do_cg(double theta, int k, const std::vector<double> &rn, int64_t *cg_its);
     int gram_host(const Segs &X, const double *Y, int64_t ldy, int k, const double *d, std::vector<double> &C);
-    int gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy);
+    int gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy, int cls);
     int solve(double *evals, double *evecs, int64_t ld, gcge_stats *stats);
 };
 
@@ -279,14 +284,15 @@ int gcge_handle_s::gram_host(const Segs &X, const double *Y, int64_t ldy, int k,
     if (e != hipSuccess) return hipfail(e, "workspace");
     const int pb = prof.begin(st);
     e = gram(op.n, X, Y, ldy, k, d, ws.small, k, ws, st);
-    prof.end(2, pb, (int64_t)m * k, st);
+    prof.end(5, pb, (int64_t)m * k, st);
     if (e != hipSuccess) return hipfail(e, "gram");
     e = stg.download(C.data(), ws.small, sizeof(double) * m * k);
     if (e != hipSuccess) return hipfail(e, "download");
     return GCGE_OK;
 }
 
-int gcge_handle_s::gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy) {
+int gcge_handle_s::gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy,
+                             int cls) {
     const int m = X.total();
     if (m == 0 || k == 0) return GCGE_OK;
     hipError_t e = ws.ensure_small(sizeof(double) * (2 * (size_t)m * k + 64));
@@ -295,7 +301,7 @@ int gcge_handle_s::gemm_host(const Segs &X, const std::vector<double> &S, int k,
     e = stg.upload(Sd, S.data(), sizeof(double) * m * k);
     const int pb = prof.begin(st);
     if (e == hipSuccess) e = gemm(op.n, X, Sd, k, k, 1.0, 0.0, Y, ldy, st);
-    prof.end(1, pb, (int64_t)m * k, st);
+    prof.end(cls, pb, (int64_t)m * k, st);
     if (e != hipSuccess) return hipfail(e, "rotation");
     return GCGE_OK;
 }
@@ -379,6 +385,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     int bs = (int)(opt_bs > 0 ? opt_bs : std::max(1, nev / 5));
     bs = std::min<int64_t>(bs, std::min<int64_t>(nev, n));
     if (bs > 128) return fail(GCGE_ERR_INVALID_ARG, "block_size above 128 is not supported");
+    prof.full_cols = bs;
     const bool mv = moving && nev > 2 * bs;
     int64_t sx = opt_sizex > 0 ? opt_sizex : std::min<int64_t>(nev + 3 * (int64_t)bs, n);
     sx = std::max<int64_t>(sx, nev);
@@ -437,7 +444,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         xh.assign((size_t)k0 * k0, 0.0);
         if (sym_eig(k0, tmp.data(), Lam.data(), xh.data(), k0) != 0)
             return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
-        rc = gemm_host(X0, xh, k0, Xb[1], ldX);
+        rc = gemm_host(X0, xh, k0, Xb[1], ldX, 3);
         if (rc) return rc;
     }
     int cur = 1, pc = 0;
@@ -503,7 +510,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
                     for (int j = i + 1; j < np_new; ++j)
                         alpha0[(size_t)i * np_new + j] = alpha0[(size_t)j * np_new + i] =
                             0.5 * (alpha0[(size_t)i * np_new + j] + alpha0[(size_t)j * np_new + i]);
-                rc = gemm_host(Vold, phc, np_new, Pb[1 - pc], ldB);
+                rc = gemm_host(Vold, phc, np_new, Pb[1 - pc], ldB, 4);
                 if (rc) return rc;
                 pc = 1 - pc;
             }
@@ -584,7 +591,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         xh.assign((size_t)dim * nwant, 0.0);
         if (sym_eig(dim, tmp.data(), w.data(), xh.data(), nwant) != 0)
             return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
-        rc = gemm_host(Vu, xh, nwant, Xb[1 - cur], ldX);
+        rc = gemm_host(Vu, xh, nwant, Xb[1 - cur], ldX, 3);
         if (rc) return rc;
         if (move) S.moves++;
         Vold = Vu;
