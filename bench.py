@@ -36,12 +36,17 @@ def log(*a):
 
 
 def row_kernel(base, s, k, tail=""):
-    """Name of the row-streaming kernel instance launched for k columns of
-    s-byte scalars (16-byte accesses: V = 16 / s scalars per lane, G lanes per row)."""
+    """Name of the row-group SpMM instance launched for k columns of s-byte
+    scalars (16-byte accesses: V = 16 / s scalars per lane, G lanes per row)."""
     v = 16 // s
     lanes = (k + v - 1) // v
     g = next(x for x in (4, 8, 16, 32, 64) if lanes <= x)
     return f"{base}<{'double' if s == 8 else 'float'}, {g}, {v}{tail}>"
+
+
+def flat_kernel(base, s, tail=""):
+    """Name of a flat CG update kernel instance for s-byte scalars."""
+    return f"{base}<{'double' if s == 8 else 'float'}, {16 // s}{tail}>"
 
 
 def class_roofline(name, p, n, nnz, s=8, bs=None):
@@ -66,9 +71,9 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
     kr = round(k)
     hbm = {"cg_spmm": lambda: (nnz * (4 + s) + 4 * (n + 1) + 2 * n * k * s,
                                row_kernel("k_spmms", s, kr, ", 0, 2") + " (CG: q = (A - theta B) p with p.q)"),
-           "cg_update_r": lambda: (3 * n * k * s, row_kernel("k_cg_update_r_v", s, kr) + " (CG: r -= alpha q, r.r)"),
+           "cg_update_r": lambda: (3 * n * k * s, flat_kernel("k_cg_update_r_pk", s, ", 4") + " (CG: r -= alpha q, r.r)"),
            "cg_update_xp": lambda: (5 * n * k * s,
-                                    row_kernel("k_cg_update_xp_v", s, kr) + " (CG: x += alpha p, p = r + beta p)")}
+                                    flat_kernel("k_cg_update_xp_flat", s) + " (CG: x += alpha p, p = r + beta p)")}
     if name in hbm:
         per_launch, kern = hbm[name]()
         achieved = per_launch / (avg_ms * 1e-3) / 1e9

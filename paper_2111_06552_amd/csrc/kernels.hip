@@ -773,6 +773,100 @@ __global__ __launch_bounds__(256) void k_cg_update_xp_v(int64_t n, int k, T *__r
     }
 }
 
+// The CG vectors are n x ld row-major blocks with ld a multiple of V, so each
+// block is one flat array of n * ld / V 16-byte vectors whose vector v holds
+// columns (v mod ld/V) * V .. + V-1 of row v / (ld/V).  The flat kernels below
+// stream those arrays with every lane busy; columns k .. ld-1 are left as they
+// are.
+
+// x += alpha p, p = r + beta p (per column): one vector per thread, one pass;
+// vectors of columns >= k are not touched.
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_cg_update_xp_flat(int64_t nvec, int ldv, int k, T *__restrict__ x,
+                                                           T *__restrict__ p, const T *__restrict__ r,
+                                                           CgState<T> cs) {
+    if (cs.flags[1] == 0) return;
+    __shared__ T sab[2][128];
+    for (int c = threadIdx.x; c < ldv * V; c += 256) {
+        sab[0][c] = c < k ? cs.alpha[c] : T(0);
+        sab[1][c] = c < k ? cs.beta[c] : T(0);
+    }
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= nvec) return;
+    const int c0 = (int)(v % ldv) * V;
+    if (c0 >= k) return;
+    T *xp = x + v * V, *pp = p + v * V;
+    const Vec<T, V> pv = vld<T, V>(pp), rv = vld<T, V>(r + v * V);
+    Vec<T, V> xv = vld<T, V>(xp), pn;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const bool on = c0 + e < k;
+        xv.v[e] = on ? fma(sab[0][c0 + e], pv.v[e], xv.v[e]) : xv.v[e];
+        pn.v[e] = on ? fma(sab[1][c0 + e], pv.v[e], rv.v[e]) : pv.v[e];
+    }
+    vst<T, V>(xp, xv);
+    vst<T, V>(pp, pn);
+}
+
+// r -= alpha q with the partial sums of r.r per column.  Thread t of a
+// work-group owns vector column t mod ldv of row offset t / ldv, so one pass
+// of the work-group covers RW = 256 / ldv consecutive whole rows (a contiguous
+// stretch of memory) with every lane but the last 256 mod ldv busy; each
+// thread takes U such passes at once (2U loads in flight) and keeps one
+// accumulator.  Lanes whose columns are all >= k do nothing.  Chunks of RW * U
+// rows follow the XCD-aware row walk; the per-thread sums are added per column
+// in row-offset order in LDS.
+template <typename T, int V, int U>
+__global__ __launch_bounds__(256) void k_cg_update_r_pk(int64_t n, int ldv, int k, const T *__restrict__ q,
+                                                        T *__restrict__ r, T *__restrict__ part, CgState<T> cs) {
+    if (cs.flags[1] == 0) return;
+    __shared__ T sh[256 * V];
+    const int tid = threadIdx.x;
+    const int RW = 256 / ldv;
+    const int ro = tid / ldv, c0 = (tid % ldv) * V;
+    const bool act = ro < RW && c0 < k;
+    const int64_t ld = (int64_t)ldv * V;
+    T al[V], acc[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        al[e] = (act && c0 + e < k) ? cs.alpha[c0 + e] : T(0);
+        acc[e] = T(0);
+    }
+    const RowWalk rw = row_walk(n, RW * U);
+    if (act) {
+        for (int64_t row0 = rw.first; row0 < rw.end; row0 += rw.stride) {
+            Vec<T, V> qv[U], rv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = min(row0 + u * RW + ro, rw.end - 1);   // clamped: always in bounds
+                qv[u] = vld<T, V>(q + row * ld + c0);
+                rv[u] = vld<T, V>(r + row * ld + c0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = row0 + u * RW + ro;
+                if (row < rw.end) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        rv[u].v[e] = fma(-al[e], qv[u].v[e], rv[u].v[e]);
+                        if (c0 + e < k) acc[e] = fma(rv[u].v[e], rv[u].v[e], acc[e]);
+                    }
+                    vst<T, V>(r + row * ld + c0, rv[u]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) sh[tid * V + e] = acc[e];
+    __syncthreads();
+    for (int c = tid; c < k; c += 256) {
+        T sum = T(0);
+        for (int o = 0; o < RW; ++o) sum += sh[(o * ldv + c / V) * V + c % V];
+        part[(size_t)c * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
 // flags[0] = active columns, flags[1] = columns with a nonzero step this iteration
 template <typename T>
 __global__ __launch_bounds__(1024) void k_cg_init_finish(const T *__restrict__ part, int nparts, int k,
@@ -928,6 +1022,12 @@ hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, 
                        hipStream_t st) {
     if (k > 128) return hipErrorInvalidValue;
     constexpr int V = 16 / sizeof(T);
+    if (cg_vec_ok<T>(k, ld, q, r, r) && ld <= 64 * V) {
+        const int ldv = (int)(ld / V);
+        const int64_t units = (n + 4 * (256 / ldv) - 1) / (4 * (256 / ldv));
+        GCGE_ROW_GO((k_cg_update_r_pk<T, V, 4>), units, nparts, n, ldv, k, q, r, part, cs);
+        return hipGetLastError();
+    }
     if (cg_vec_ok<T>(k, ld, q, r, r)) {
         const int lanes = (k + V - 1) / V;
         const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
@@ -952,6 +1052,15 @@ template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st) {
     if (k > 128) return hipErrorInvalidValue;
     constexpr int V = 16 / sizeof(T);
+    if (cg_vec_ok<T>(k, ld, x, p, r) && ld <= 128) {
+        const int64_t nvec = n * (ld / V);
+        const int64_t blocks = (nvec + 255) / 256;
+        if (blocks < (int64_t)1 << 31) {
+            hipLaunchKernelGGL((k_cg_update_xp_flat<T, V>), dim3((unsigned)blocks), dim3(256), 0, st, nvec,
+                               (int)(ld / V), k, x, p, r, cs);
+            return hipGetLastError();
+        }
+    }
     if (cg_vec_ok<T>(k, ld, x, p, r)) {
         const int lanes = (k + V - 1) / V;
         const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;

@@ -158,6 +158,29 @@ def test_cg_fp64_matches_oracle(g, maxit):
     assert np.max(np.abs(host(D) - ref)) < 1e-10 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("k", [1, 7, 26, 50, 100])
+def test_cg_fp64_block_widths(g, k):
+    """Every stored-width layout of the CG vectors (flat kernels with 1 to 13
+    slots per thread, and the row-group kernels beyond), ragged row counts."""
+    A = wl.laplace3d_7pt(11)
+    d = wl.diag_uniform(A.n)
+    R = RNG.standard_normal((A.n, k))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), dev(d), 30.0, dev(R), maxit=6, rel_tol=1e-3)
+    ref, its_r = orc.cg_columnwise(A, "diag", d, 30.0, R, maxit=6, rel_tol=1e-3)
+    assert np.array_equal(its, its_r)
+    assert np.max(np.abs(host(D) - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k", [13, 50, 100])
+def test_cg_mixed_block_widths(g, k):
+    A = wl.laplace3d_7pt(11)
+    R = RNG.standard_normal((A.n, k))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), None, 0.0, dev(R), maxit=6, rel_tol=0.0, precision="mixed")
+    ref, _ = orc.cg_columnwise(A, "identity", None, 0.0, R, maxit=6, rel_tol=0.0)
+    assert np.max(np.abs(host(D) - ref)) < 1e-4 * np.max(np.abs(ref))
+    assert np.all(its == 6)
+
+
 def test_cg_mixed_precision_close_to_oracle(g):
     A = wl.laplace3d_7pt(10)
     R = RNG.standard_normal((A.n, 10))
