@@ -126,6 +126,9 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "check"        [1]     compute max_rel_residual and orth_error at the end
  *  "profile"      [0]     time the launches of the main kernel classes with HIP events
  *                         (fields prof_* of gcge_stats)
+ *  "dense_eig"    [1]     small Rayleigh-Ritz eigenproblem on the device (gcge_dense_eig)
+ *                         when its order is at most 1024; 0 solves it on the host
+ *                         (gcge_small_eigh)
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
 
@@ -238,6 +241,18 @@ int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq
  * (destroyed); w: host double[n] ascending; z: host n x nwant row-major, the
  * eigenvectors of the nwant smallest eigenvalues as columns (may be NULL). */
 int gcge_small_eigh(int n, double *a, double *w, double *z, int nwant);
+
+/* Device dense symmetric eigensolver of the Rayleigh-Ritz problem (the paper
+ * calls LAPACK dsyevx on the host): Householder tridiagonalization,
+ * multisection for the eigenvalues, inverse iteration (clusters
+ * Gram-Schmidt-orthogonalized) and back-transformation, then Newton-Schulz
+ * re-orthonormalization of the eigenvectors.  a: device n x n row-major
+ * symmetric (lda, not modified); w: device double[nwant], the nwant smallest
+ * eigenvalues ascending; x: device n x nwant row-major (ldx), the matching
+ * orthonormal eigenvectors as columns.  1 <= nwant <= n <= 1024 (INVALID_ARG
+ * otherwise).  Asynchronous on stream. */
+int gcge_dense_eig(int n, const double *a, int64_t lda, int nwant, double *w, double *x, int64_t ldx,
+                   void *stream);
 
 /* Host-only STEP 5: coefficients phat of the next P block from the Ritz
  * coefficient vectors xhat (dim x nx, row-major): columns shift ..

@@ -95,6 +95,7 @@ def _b_args(B):
 
 
 _INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
+             "dense_eig",
              "profile"}
 _DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol"}
 
@@ -367,6 +368,21 @@ def small_eigh(M, nwant: int | None = None):
     _lib.check(_L().gcge_small_eigh(n, a.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
                                     z.ctypes.data_as(ctypes.c_void_p) if nwant else None, nwant))
     return w, z
+
+
+def dense_eig(M: torch.Tensor, nwant: int | None = None):
+    """Device dense symmetric eigensolver: (w [nwant] ascending, X [n, nwant]), both on M's device."""
+    _check_dev(M, torch.float64, "M")
+    n = M.shape[0]
+    if M.dim() != 2 or M.shape[1] != n:
+        raise ValueError("M must be square")
+    nwant = n if nwant is None else int(nwant)
+    pm, ldm = _rowmajor(M, "M")
+    w = torch.empty(nwant, dtype=torch.float64, device=M.device)
+    X = torch.empty((n, nwant), dtype=torch.float64, device=M.device)
+    px, ldx = _rowmajor(X, "X")
+    _lib.check(_L().gcge_dense_eig(n, pm, ldm, nwant, _p(w), px, ldx, ctypes.c_void_p(_stream(M.device))))
+    return w, X
 
 
 def p_hat(xhat, shift: int, n_old: int, n_new: int, drop_tol: float = 1e-10):

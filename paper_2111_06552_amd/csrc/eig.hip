@@ -1,0 +1,453 @@
+// Dense symmetric eigensolver on the device for the reduced Rayleigh-Ritz
+// problem of STEP 3 (Section 3.2; the paper calls LAPACK dsyevx on the host).
+//
+//   1. Householder reduction of the n x n matrix to tridiagonal form T by one
+//      work-group (the matrix stays in L2; vectors in LDS).
+//   2. The nwant smallest eigenvalues of T by multisection: one wave per
+//      eigenvalue, 64 Sturm counts per round (one per lane).
+//   3. Their eigenvectors by inverse iteration with a partially pivoted LU of
+//      T - lambda I; eigenvalues closer than a cluster tolerance are handled by
+//      one work-group in order, each vector orthogonalized against the earlier
+//      ones of its cluster (classical Gram-Schmidt, twice).
+//   4. Back-transformation by the Householder reflectors.
+//   5. Two Newton-Schulz steps X <- X (3 I - X^T X) / 2 with the block Gram
+//      and GEMM kernels, which restore orthonormality to rounding (inverse
+//      iteration leaves eps ||T|| / gap between vectors of distinct
+//      eigenvalues) while keeping X^T A X diagonal to O(eps ||T||).
+//
+// Every step is deterministic (fixed reduction orders, counter-based start
+// vectors).
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace gcge {
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wmin(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over a work-group of NW waves, identical in every thread, fixed order.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    v = wsum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// 1. Householder tridiagonalization, one work-group of 1024 threads.
+// a: n x n symmetric, row-major (lda).  Step k reflects rows/columns k+1..n-1
+// with H_k = I - tau_k v v^T (v[0] = 1) chosen from row k; v is stored over
+// row k (columns k+1..n-1) for the back-transformation.  d, e: diagonal and
+// off-diagonal of T; tau[k] for k < n-2.
+// ---------------------------------------------------------------------------
+constexpr int TRI_T = 1024, TRI_W = TRI_T / 64;
+
+__global__ __launch_bounds__(TRI_T) void k_tridiag(int n, double *__restrict__ a, int64_t lda,
+                                                    double *__restrict__ d, double *__restrict__ e,
+                                                    double *__restrict__ tau) {
+    extern __shared__ double sm[];
+    double *v = sm, *p = sm + n;
+    __shared__ double red[TRI_W];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        double *x = a + (int64_t)k * lda + (k + 1);
+        double s = 0.0;
+        for (int i = 1 + tid; i < m; i += TRI_T) s += x[i] * x[i];
+        s = block_sum<TRI_W>(s, red);
+        const double alpha = x[0];
+        if (s == 0.0) {
+            if (tid == 0) {
+                tau[k] = 0.0;
+                e[k] = alpha;
+                d[k] = a[(int64_t)k * lda + k];
+            }
+            __syncthreads();
+            continue;
+        }
+        const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        const double t = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+        for (int i = tid; i < m; i += TRI_T) v[i] = (i == 0) ? 1.0 : x[i] * sc;
+        __syncthreads();
+        for (int i = tid; i < m; i += TRI_T) x[i] = v[i];
+        if (tid == 0) {
+            tau[k] = t;
+            e[k] = beta;
+            d[k] = a[(int64_t)k * lda + k];
+        }
+        double *A22 = a + (int64_t)(k + 1) * lda + (k + 1);
+        // p = t A22 v, one wave per row
+        for (int i = wave; i < m; i += TRI_W) {
+            const double *row = A22 + (int64_t)i * lda;
+            double acc = 0.0;
+            for (int j = lane; j < m; j += 64) acc += row[j] * v[j];
+            acc = wsum(acc);
+            if (lane == 0) p[i] = t * acc;
+        }
+        __syncthreads();
+        double pv = 0.0;
+        for (int i = tid; i < m; i += TRI_T) pv += p[i] * v[i];
+        pv = block_sum<TRI_W>(pv, red);
+        const double K = -0.5 * t * pv;
+        for (int i = tid; i < m; i += TRI_T) p[i] += K * v[i];   // p now holds w
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        for (int i = wave; i < m; i += TRI_W) {
+            double *row = A22 + (int64_t)i * lda;
+            const double vi = v[i], wi = p[i];
+            for (int j = lane; j < m; j += 64) row[j] -= vi * p[j] + wi * v[j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (n >= 2) {
+            d[n - 2] = a[(int64_t)(n - 2) * lda + (n - 2)];
+            e[n - 2] = a[(int64_t)(n - 2) * lda + (n - 1)];
+            tau[n - 2] = 0.0;
+        }
+        d[n - 1] = a[(int64_t)(n - 1) * lda + (n - 1)];
+    }
+}
+
+// Gershgorin interval, norm bound and pivot floor of T, as every wave of the
+// later kernels computes them (identically).
+struct TBounds {
+    double lo, hi, tnorm, pivmin;
+};
+__device__ TBounds t_bounds(int n, const double *d, const double *e) {
+    const int lane = threadIdx.x % 64;
+    double lo = INFINITY, hi = -INFINITY, e2 = 0.0;
+    for (int r = lane; r < n; r += 64) {
+        const double off = (r > 0 ? fabs(e[r - 1]) : 0.0) + (r + 1 < n ? fabs(e[r]) : 0.0);
+        lo = fmin(lo, d[r] - off);
+        hi = fmax(hi, d[r] + off);
+        if (r + 1 < n) e2 = fmax(e2, e[r] * e[r]);
+    }
+    TBounds b;
+    b.lo = wmin(lo);
+    b.hi = wmax(hi);
+    b.tnorm = fmax(fabs(b.lo), fabs(b.hi));
+    b.pivmin = DBL_MIN * fmax(1.0, wmax(e2));
+    const double pad = 2.0 * EPS * b.tnorm + 4.0 * b.pivmin;
+    b.lo -= pad;
+    b.hi += pad;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Eigenvalue i (0-based, ascending) of T by multisection: one wave per
+// eigenvalue; each round splits the bracket into 65 parts and lane l counts
+// the eigenvalues below the l-th split point (Sturm sequence).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_bisect(int n, const double *__restrict__ d, const double *__restrict__ e,
+                                               int nwant, double *__restrict__ w) {
+    extern __shared__ double sm[];
+    double *sd = sm, *se2 = sm + n;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    for (int r = lane; r < n; r += 64) {
+        sd[r] = d[r];
+        se2[r] = (r + 1 < n) ? e[r] * e[r] : 0.0;
+    }
+    __syncthreads();
+    const TBounds b = t_bounds(n, d, e);
+    double lo = b.lo, hi = b.hi;
+    for (int round = 0; round < 24; ++round) {
+        if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + 2.0 * b.pivmin) break;
+        const double h = hi - lo;
+        const double x = lo + h * (double)(lane + 1) / 65.0;
+        int cnt = 0;
+        double q = sd[0] - x;
+        if (fabs(q) < b.pivmin) q = -b.pivmin;
+        cnt += q < 0.0;
+        for (int r = 1; r < n; ++r) {
+            q = (sd[r] - x) - se2[r - 1] / q;
+            if (fabs(q) < b.pivmin) q = -b.pivmin;
+            cnt += q < 0.0;
+        }
+        const unsigned long long mask = __ballot(cnt > i);
+        if (mask == 0ull) {
+            lo = lo + h * 64.0 / 65.0;
+        } else {
+            const int f = __ffsll((long long)mask) - 1;
+            const double nhi = lo + h * (double)(f + 1) / 65.0;
+            const double nlo = (f > 0) ? lo + h * (double)f / 65.0 : lo;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (lane == 0) w[i] = 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Inverse iteration.  Work-group i (one wave) acts only when eigenvalue i
+// starts a cluster (i == 0 or w[i] - w[i-1] > ctol); it then computes the
+// vectors of the whole cluster in order.  LU of T - s I with row interchanges
+// (a tridiagonal U with two superdiagonals), three solves from a start vector
+// drawn from SplitMix64, each followed by two Gram-Schmidt passes against the
+// earlier vectors of the cluster and normalization.  Z column-major (ldz).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(64) void k_invit(int n, const double *__restrict__ d, const double *__restrict__ e,
+                                              int nwant, const double *__restrict__ w, double ctol_rel,
+                                              double *__restrict__ Z, int64_t ldz) {
+    const int i = blockIdx.x, lane = threadIdx.x;
+    const TBounds b = t_bounds(n, d, e);
+    const double ctol = ctol_rel * b.tnorm;
+    if (i > 0 && w[i] - w[i - 1] <= ctol) return;   // not the first of its cluster
+    int j = i + 1;
+    while (j < nwant && w[j] - w[j - 1] <= ctol) ++j;
+    extern __shared__ double sm[];
+    double *u1 = sm, *u2 = sm + n, *u3 = sm + 2 * n, *ml = sm + 3 * n, *z = sm + 4 * n;
+    int *piv = (int *)(sm + 5 * n);
+    const double tiny = EPS * b.tnorm + b.pivmin;
+    double sprev = -INFINITY;
+    for (int mbr = i; mbr < j; ++mbr) {
+        double s = w[mbr];
+        if (s <= sprev) s = sprev + 10.0 * EPS * b.tnorm;   // separate equal shifts
+        sprev = s;
+        if (lane == 0) {
+            // LU with partial pivoting of the tridiagonal T - s I
+            double ar = d[0] - s, br = (n > 1) ? e[0] : 0.0;
+            for (int r = 0; r + 1 < n; ++r) {
+                const double cr = e[r];                       // subdiagonal entry (r+1, r)
+                const double an = d[r + 1] - s;               // diagonal of row r+1
+                const double bn = (r + 2 < n) ? e[r + 1] : 0.0;   // (r+1, r+2)
+                if (fabs(ar) >= fabs(cr)) {
+                    const double aa = (fabs(ar) < tiny) ? copysign(tiny, ar) : ar;
+                    const double l = cr / aa;
+                    u1[r] = aa;
+                    u2[r] = br;
+                    u3[r] = 0.0;
+                    ml[r] = l;
+                    piv[r] = 0;
+                    ar = an - l * br;
+                    br = bn;
+                } else {
+                    const double l = ar / cr;
+                    u1[r] = (fabs(cr) < tiny) ? copysign(tiny, cr) : cr;
+                    u2[r] = an;
+                    u3[r] = bn;
+                    ml[r] = l;
+                    piv[r] = 1;
+                    ar = br - l * an;
+                    br = -l * bn;
+                }
+            }
+            u1[n - 1] = (fabs(ar) < tiny) ? copysign(tiny, ar) : ar;
+            ml[n - 1] = 0.0;
+            piv[n - 1] = 0;
+        }
+        for (int r = lane; r < n; r += 64) {
+            const uint64_t h = mix64((uint64_t)0x5eed + ((uint64_t)mbr * (uint64_t)n + (uint64_t)r + 1) *
+                                                             0x9e3779b97f4a7c15ull);
+            z[r] = 2.0 * ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+        }
+        __syncthreads();
+        for (int it = 0; it < 3; ++it) {
+            if (lane == 0) {
+                // forward: row interchanges and L
+                for (int r = 0; r + 1 < n; ++r) {
+                    if (piv[r]) {
+                        const double t = z[r];
+                        z[r] = z[r + 1];
+                        z[r + 1] = t;
+                    }
+                    z[r + 1] -= ml[r] * z[r];
+                }
+                // back substitution with U
+                z[n - 1] /= u1[n - 1];
+                if (n >= 2) z[n - 2] = (z[n - 2] - u2[n - 2] * z[n - 1]) / u1[n - 2];
+                for (int r = n - 3; r >= 0; --r) z[r] = (z[r] - u2[r] * z[r + 1] - u3[r] * z[r + 2]) / u1[r];
+            }
+            __syncthreads();
+            // scale, then orthogonalize against the earlier cluster vectors (twice)
+            double nr = 0.0;
+            for (int r = lane; r < n; r += 64) nr += z[r] * z[r];
+            nr = wsum(nr);
+            const double inv = (nr > 0.0) ? 1.0 / sqrt(nr) : 0.0;
+            for (int r = lane; r < n; r += 64) z[r] *= inv;
+            for (int pass = 0; pass < 2 && mbr > i; ++pass) {
+                for (int q = i; q < mbr; ++q) {
+                    const double *zq = Z + (int64_t)q * ldz;
+                    double c = 0.0;
+                    for (int r = lane; r < n; r += 64) c += zq[r] * z[r];
+                    c = wsum(c);
+                    for (int r = lane; r < n; r += 64) z[r] -= c * zq[r];
+                }
+                double n2 = 0.0;
+                for (int r = lane; r < n; r += 64) n2 += z[r] * z[r];
+                n2 = wsum(n2);
+                const double in2 = (n2 > 0.0) ? 1.0 / sqrt(n2) : 0.0;
+                for (int r = lane; r < n; r += 64) z[r] *= in2;
+            }
+            __syncthreads();
+        }
+        double *zo = Z + (int64_t)mbr * ldz;
+        for (int r = lane; r < n; r += 64) zo[r] = z[r];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. x = H_0 H_1 ... H_{n-3} z for NC columns per work-group; output row-major.
+// ---------------------------------------------------------------------------
+constexpr int BT_T = 256, BT_W = BT_T / 64, BT_NC = 4;
+
+__global__ __launch_bounds__(BT_T) void k_backtr(int n, const double *__restrict__ a, int64_t lda,
+                                                 const double *__restrict__ tau, int nwant,
+                                                 const double *__restrict__ Z, int64_t ldz,
+                                                 double *__restrict__ X, int64_t ldx) {
+    extern __shared__ double sm[];   // BT_NC columns of n
+    __shared__ double red[BT_W][BT_NC];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int c0 = blockIdx.x * BT_NC;
+    const int nc = min(BT_NC, nwant - c0);
+    for (int c = 0; c < BT_NC; ++c)
+        for (int r = tid; r < n; r += BT_T) sm[c * n + r] = (c < nc) ? Z[(int64_t)(c0 + c) * ldz + r] : 0.0;
+    __syncthreads();
+    for (int k = n - 3; k >= 0; --k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        const int m = n - k - 1;
+        const double *v = a + (int64_t)k * lda + (k + 1);
+        double s[BT_NC];
+#pragma unroll
+        for (int c = 0; c < BT_NC; ++c) s[c] = 0.0;
+        for (int r = tid; r < m; r += BT_T) {
+            const double vr = v[r];
+#pragma unroll
+            for (int c = 0; c < BT_NC; ++c) s[c] += vr * sm[c * n + k + 1 + r];
+        }
+#pragma unroll
+        for (int c = 0; c < BT_NC; ++c) {
+            s[c] = wsum(s[c]);
+            if (lane == 0) red[wave][c] = s[c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < BT_NC; ++c) {
+            double tot = 0.0;
+#pragma unroll
+            for (int q = 0; q < BT_W; ++q) tot += red[q][c];
+            s[c] = t * tot;
+        }
+        for (int r = tid; r < m; r += BT_T) {
+            const double vr = v[r];
+#pragma unroll
+            for (int c = 0; c < BT_NC; ++c) sm[c * n + k + 1 + r] -= s[c] * vr;
+        }
+        __syncthreads();
+    }
+    for (int r = tid; r < n; r += BT_T)
+        for (int c = 0; c < nc; ++c) X[(int64_t)r * ldx + c0 + c] = sm[c * n + r];
+}
+
+// M = 1.5 I - 0.5 G (m x m, row-major, ld)
+__global__ __launch_bounds__(256) void k_ns_coef(int m, double *__restrict__ G, int64_t ld) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)m * m) return;
+    const int r = (int)(idx / m), c = (int)(idx % m);
+    double *g = G + (int64_t)r * ld + c;
+    *g = (r == c ? 1.5 : 0.0) - 0.5 * *g;
+}
+
+}  // namespace
+
+hipError_t DenseEigWork::ensure(int n, int nwant) {
+    const size_t need = (size_t)n * n + 3 * (size_t)n + 32 + 3 * (size_t)n * nwant + (size_t)nwant * nwant + 64;
+    if (need <= cap) return hipSuccess;
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc(&buf, need * sizeof(double));
+    if (e != hipSuccess) return e;
+    cap = need;
+    return hipSuccess;
+}
+
+void DenseEigWork::release() {
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+}
+
+hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, double *X, int64_t ldx,
+                     DenseEigWork &dw, Workspace &ws, hipStream_t st) {
+    if (n <= 0 || nwant <= 0) return hipSuccess;
+    if (nwant > n || n > DENSE_EIG_MAX || ldx < nwant || lda < n) return hipErrorInvalidValue;
+    hipError_t e = dw.ensure(n, nwant);
+    if (e != hipSuccess) return e;
+    double *a = dw.buf;                          // n x n working copy, then the reflectors
+    double *dg = a + (size_t)n * n;              // diagonal of T
+    double *off = dg + n + 8;                    // off-diagonal of T
+    double *tau = off + n + 8;                   // reflector scalars
+    double *Z = tau + n + 8;                     // eigenvectors of T, column-major n x nwant
+    double *X1 = Z + (size_t)n * nwant;          // row-major n x nwant scratch
+    double *X2 = X1 + (size_t)n * nwant;         // row-major n x nwant scratch
+    double *G = X2 + (size_t)n * nwant;          // nwant x nwant
+    e = hipMemcpy2DAsync(a, sizeof(double) * n, A, sizeof(double) * lda, sizeof(double) * n, n,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TRI_T), sizeof(double) * 2 * n, st, n, a, (int64_t)n, dg, off,
+                       tau);
+    hipLaunchKernelGGL(k_bisect, dim3(nwant), dim3(64), sizeof(double) * 2 * n, st, n, dg, off, nwant, w);
+    const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n + 64;
+    hipLaunchKernelGGL(k_invit, dim3(nwant), dim3(64), inv_lds, st, n, dg, off, nwant, w, 1e-10, Z, (int64_t)n);
+    const int nb = (nwant + BT_NC - 1) / BT_NC;
+    hipLaunchKernelGGL(k_backtr, dim3(nb), dim3(BT_T), sizeof(double) * BT_NC * n, st, n, a, (int64_t)n, tau,
+                       nwant, Z, (int64_t)n, X1, (int64_t)nwant);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // two Newton-Schulz steps: X1 -> X2 -> X
+    const double *src = X1;
+    for (int it = 0; it < 2; ++it) {
+        Segs S;
+        S.add(src, nwant, nwant);
+        e = gram(n, S, src, nwant, nwant, nullptr, G, nwant, ws, st);
+        if (e != hipSuccess) return e;
+        const int64_t cnt = (int64_t)nwant * nwant;
+        hipLaunchKernelGGL(k_ns_coef, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nwant, G,
+                           (int64_t)nwant);
+        double *dst = (it == 0) ? X2 : X;
+        const int64_t ldd = (it == 0) ? nwant : ldx;
+        e = gemm(n, S, G, nwant, nwant, 1.0, 0.0, dst, ldd, st);
+        if (e != hipSuccess) return e;
+        src = X2;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gcge

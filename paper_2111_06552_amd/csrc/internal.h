@@ -147,6 +147,24 @@ hipError_t pattern_grad(int64_t n, const int32_t *rowptr, const int32_t *colind,
 hipError_t diag_grad(int64_t n, const double *X, int64_t ldx, int nev, const double *w, double *gd,
                      hipStream_t st);
 
+// ------------------------------------------------------------ device dense
+// Largest matrix order of the device eigensolver (LDS per work-group).
+constexpr int DENSE_EIG_MAX = 1024;
+
+// Grow-only device scratch of dense_eig.
+struct DenseEigWork {
+    double *buf = nullptr;
+    size_t cap = 0;   // doubles
+    hipError_t ensure(int n, int nwant);
+    void release();
+};
+
+// The nwant smallest eigenpairs of the symmetric n x n matrix A (device,
+// row-major, lda; not modified): w (device, ascending) and X (device, n x
+// nwant row-major, ldx) with X^T X = I.  Asynchronous on st.
+hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, double *X, int64_t ldx,
+                     DenseEigWork &dw, Workspace &ws, hipStream_t st);
+
 // ------------------------------------------------------------- host dense
 // Symmetric eigensolver: a (n x n, row-major, destroyed), w ascending, z (n x
 // nwant row-major) eigenvectors of the nwant smallest eigenvalues.  Returns 0

@@ -213,6 +213,10 @@ struct gcge_handle_s {
     hipEvent_t ev = nullptr;
     int profile = 0;
     KProf prof;
+    int dense_eig_opt = 1;
+    DenseEigWork eigw;
+    double *rrbuf = nullptr;   // device: Abar, its eigenvalues and eigenvectors
+    size_t rrcap = 0;
     // results of the last solve
     bool have_res = false;
     std::vector<double> res_lam;   // ascending
@@ -232,8 +236,53 @@ struct gcge_handle_s {
     int do_cg(double theta, int k, const std::vector<double> &rn, int64_t *cg_its);
     int gram_host(const Segs &X, const double *Y, int64_t ldy, int k, const double *d, std::vector<double> &C);
     int gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy, int cls);
+    int ritz_rotate(const Segs &V, const std::vector<double> &Ab, int dim, int nwant, std::vector<double> &w,
+                    std::vector<double> &xh, double *Y, int64_t ldy);
     int solve(double *evals, double *evecs, int64_t ld, gcge_stats *stats);
 };
+
+// Ritz pairs of the symmetric dim x dim matrix Ab (host, row-major): the nwant
+// smallest eigenvalues (w, host) with their coefficient vectors (xh, host,
+// dim x nwant row-major), and the rotation Y = V xh on the device.  The
+// eigenproblem is solved on the device (dense_eig) unless the option
+// dense_eig is 0 or dim exceeds DENSE_EIG_MAX.
+int gcge_handle_s::ritz_rotate(const Segs &V, const std::vector<double> &Ab, int dim, int nwant,
+                               std::vector<double> &w, std::vector<double> &xh, double *Y, int64_t ldy) {
+    xh.assign((size_t)dim * nwant, 0.0);
+    if (dense_eig_opt && dim <= DENSE_EIG_MAX) {
+        const size_t o_w = ((size_t)dim * dim + 31) / 32 * 32;
+        const size_t o_x = o_w + ((size_t)nwant + 31) / 32 * 32;
+        const size_t need = o_x + (size_t)dim * nwant + 32;
+        if (need > rrcap) {
+            if (rrbuf) (void)hipFree(rrbuf);
+            rrbuf = nullptr;
+            rrcap = 0;
+            hipError_t e = hipMalloc(&rrbuf, need * sizeof(double));
+            if (e != hipSuccess) return hipfail(e, "Rayleigh-Ritz buffers");
+            rrcap = need;
+        }
+        double *ad = rrbuf, *wd = rrbuf + o_w, *xd = rrbuf + o_x;
+        hipError_t e = stg.upload(ad, Ab.data(), sizeof(double) * dim * dim);
+        if (e == hipSuccess) e = dense_eig(dim, ad, dim, nwant, wd, xd, nwant, eigw, ws, st);
+        if (e != hipSuccess) return hipfail(e, "dense eigensolve");
+        const int pb = prof.begin(st);
+        e = gemm(op.n, V, xd, nwant, nwant, 1.0, 0.0, Y, ldy, st);
+        prof.end(3, pb, (int64_t)dim * nwant, st);
+        if (e != hipSuccess) return hipfail(e, "rotation");
+        w.assign(nwant, 0.0);
+        e = stg.download(w.data(), wd, sizeof(double) * nwant);
+        if (e == hipSuccess) e = stg.download(xh.data(), xd, sizeof(double) * dim * nwant);
+        if (e != hipSuccess) return hipfail(e, "download");
+        for (int i = 0; i < nwant; ++i)
+            if (!std::isfinite(w[i])) return fail(GCGE_ERR_INTERNAL, "dense eigensolve produced a non-finite value");
+        return GCGE_OK;
+    }
+    std::vector<double> tmp = Ab;
+    w.assign(dim, 0.0);
+    if (sym_eig(dim, tmp.data(), w.data(), xh.data(), nwant) != 0)
+        return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
+    return gemm_host(V, xh, nwant, Y, ldy, 3);
+}
 
 int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
     if (bs == cfg_bs && capx == cfg_capx && prec == cfg_prec) return GCGE_OK;
@@ -439,12 +488,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         if (rc) return rc;
         for (int i = 0; i < k0; ++i)
             for (int j = i + 1; j < k0; ++j) Ab[(size_t)i * k0 + j] = Ab[(size_t)j * k0 + i] = 0.5 * (Ab[(size_t)i * k0 + j] + Ab[(size_t)j * k0 + i]);
-        std::vector<double> tmp = Ab;
-        Lam.assign(k0, 0.0);
-        xh.assign((size_t)k0 * k0, 0.0);
-        if (sym_eig(k0, tmp.data(), Lam.data(), xh.data(), k0) != 0)
-            return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
-        rc = gemm_host(X0, xh, k0, Xb[1], ldX, 3);
+        rc = ritz_rotate(X0, Ab, k0, k0, Lam, xh, Xb[1], ldX);
         if (rc) return rc;
     }
     int cur = 1, pc = 0;
@@ -587,11 +631,8 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
             }
         const bool move = mv && nx <= bs;
         const int nwant = move ? dim : nx;
-        std::vector<double> tmp = Ab, w(dim);
-        xh.assign((size_t)dim * nwant, 0.0);
-        if (sym_eig(dim, tmp.data(), w.data(), xh.data(), nwant) != 0)
-            return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
-        rc = gemm_host(Vu, xh, nwant, Xb[1 - cur], ldX, 3);
+        std::vector<double> w;
+        rc = ritz_rotate(Vu, Ab, dim, nwant, w, xh, Xb[1 - cur], ldX);
         if (rc) return rc;
         if (move) S.moves++;
         Vold = Vu;
@@ -755,6 +796,7 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "seed") { h->seed = (uint64_t)v; }
     else if (k == "check") { if (v != 0 && v != 1) return bad(); h->check = (int)v; }
     else if (k == "profile") { if (v != 0 && v != 1) return bad(); h->profile = (int)v; }
+    else if (k == "dense_eig") { if (v != 0 && v != 1) return bad(); h->dense_eig_opt = (int)v; }
     else return h->fail(GCGE_ERR_INVALID_ARG, "unknown option " + k);
     return GCGE_OK;
 }
@@ -850,6 +892,8 @@ extern "C" void gcge_destroy(gcge_handle h) {
     if (h->pinned_flag) (void)hipHostFree(h->pinned_flag);
     if (h->ev) (void)hipEventDestroy(h->ev);
     h->prof.release();
+    h->eigw.release();
+    if (h->rrbuf) (void)hipFree(h->rrbuf);
     delete h;
 }
 
@@ -866,6 +910,7 @@ struct StepCtx {
     std::mutex mu;
     Workspace ws;
     Stager stg;
+    DenseEigWork eig;
 };
 
 StepCtx &step_ctx() {
@@ -1172,6 +1217,18 @@ extern "C" int gcge_small_eigh(int n, double *a, double *w, double *z, int nwant
     } catch (...) {
         return step_fail(GCGE_ERR_OOM, "gcge_small_eigh: host allocation failed");
     }
+}
+
+extern "C" int gcge_dense_eig(int n, const double *a, int64_t lda, int nwant, double *w, double *x, int64_t ldx,
+                              void *stream) {
+    if (n < 1 || n > DENSE_EIG_MAX || nwant < 1 || nwant > n || !a || !w || !x || lda < n || ldx < nwant)
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_dense_eig: invalid argument");
+    StepCtx &C = step_ctx();
+    std::lock_guard<std::mutex> lk(C.mu);
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dense_eig(n, a, lda, nwant, w, x, ldx, C.eig, C.ws, st);
+    if (e != hipSuccess) return step_hip(e, "gcge_dense_eig");
+    return GCGE_OK;
 }
 
 extern "C" int gcge_p_hat(int dim, int nx, const double *xhat, int shift, int n_old, int n_new, double drop_tol,

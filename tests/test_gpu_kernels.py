@@ -237,3 +237,97 @@ def test_pattern_grad_matches_formula(g):
     ref = orc.eig_grad(A, X, np.ones(37), w)
     bound = orc.eig_grad(A, np.abs(X), np.ones(37), np.abs(w))
     assert np.all(np.abs(gd - ref) <= 1e-13 * bound)
+
+
+# ------------------------------------------------------- device dense eigensolver
+
+def _check_dense_eig(g, A, nwant, ref=None):
+    """Eigenvalues against the oracle's Jacobi, residuals, orthonormality and
+    per-cluster subspaces of the device eigensolver's output."""
+    n = A.shape[0]
+    w, X = g.dense_eig(dev(A), nwant)
+    w, X = host(w), host(X)
+    wo, Vo = orc.jacobi_eigh(A) if ref is None else ref
+    nrm = max(np.max(np.abs(wo)), 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(w - wo[:nwant])) <= 5e-13 * nrm
+    assert np.max(np.abs(X.T @ X - np.eye(nwant))) <= 1e-13
+    R = A @ X - X * w[None, :]
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-12 * nrm
+    # X^T A X diagonal up to rounding (the structured Rayleigh-Ritz matrix relies on it)
+    H = X.T @ A @ X
+    assert np.max(np.abs(H - np.diag(np.diag(H)))) <= 1e-12 * nrm
+    # subspaces of clusters not cut by nwant
+    i = 0
+    while i < nwant:
+        j = i + 1
+        while j < n and wo[j] - wo[j - 1] <= 1e-8 * nrm:
+            j += 1
+        if j <= nwant:
+            s = np.linalg.svd(X[:, i:j].T @ Vo[:, i:j], compute_uv=False)   # test-only
+            assert s.min() > 1 - 1e-9, (i, j, s)
+        i = j
+    return w, X
+
+
+@pytest.mark.parametrize("n,nwant", [(1, 1), (2, 2), (3, 2), (17, 17), (64, 40), (200, 150), (450, 350)])
+def test_dense_eig_random_symmetric(g, n, nwant):
+    M = RNG.standard_normal((n, n))
+    A = (M + M.T) * 10.0
+    _check_dense_eig(g, A, nwant)
+
+
+def test_dense_eig_exact_multiplicities(g):
+    """Q diag(lam) Q^T with eigenvalues of multiplicity up to 6, and a diagonal
+    matrix with repeated entries (already tridiagonal, every reflector empty)."""
+    n = 120
+    lam = np.repeat(np.arange(1.0, 21.0) ** 2, 6)
+    Q, _ = np.linalg.qr(RNG.standard_normal((n, n)))   # test-only input construction
+    A = (Q * lam[None, :]) @ Q.T
+    A = 0.5 * (A + A.T)
+    _check_dense_eig(g, A, 90, ref=(lam, Q))
+    D = np.diag(np.repeat([3.0, 1.0, 2.0, 1.0], 8))
+    wo = np.sort(np.diag(D))
+    Vo = np.eye(32)[:, np.argsort(np.diag(D), kind="stable")]
+    _check_dense_eig(g, D, 32, ref=(wo, Vo))
+
+
+def test_dense_eig_rayleigh_ritz_structure(g):
+    """The structured Abar of STEP 3: diagonal Ritz block, zero X-P block,
+    dense P and W blocks, graded couplings."""
+    nx, bs = 300, 50
+    lam = np.sort(30.0 + 600.0 * RNG.random(nx))
+    n = nx + 2 * bs
+    A = np.zeros((n, n))
+    A[:nx, :nx] = np.diag(lam)
+    a0 = RNG.standard_normal((bs, bs))
+    A[nx:nx + bs, nx:nx + bs] = 300.0 * np.eye(bs) + 20.0 * (a0 + a0.T)
+    a3 = RNG.standard_normal((bs, bs))
+    A[nx + bs:, nx + bs:] = 3000.0 * np.eye(bs) + 200.0 * (a3 + a3.T)
+    a1 = RNG.standard_normal((nx, bs)) * np.logspace(-8, 1, nx)[:, None]
+    A[:nx, nx + bs:] = a1
+    A[nx + bs:, :nx] = a1.T
+    a2 = 5.0 * RNG.standard_normal((bs, bs))
+    A[nx:nx + bs, nx + bs:] = a2
+    A[nx + bs:, nx:nx + bs] = a2.T
+    _check_dense_eig(g, A, nx)
+    _check_dense_eig(g, A, n)
+
+
+def test_dense_eig_graded_and_deterministic(g):
+    n = 96
+    Q, _ = np.linalg.qr(RNG.standard_normal((n, n)))   # test-only input construction
+    lam = np.sort(np.concatenate([-np.logspace(-8, 4, n // 2), np.logspace(-8, 4, n - n // 2)]))
+    A = (Q * lam[None, :]) @ Q.T
+    A = 0.5 * (A + A.T)
+    w1, X1 = g.dense_eig(dev(A), n)
+    w2, X2 = g.dense_eig(dev(A), n)
+    assert torch.equal(w1, w2) and torch.equal(X1, X2)
+    _check_dense_eig(g, A, n, ref=(lam, Q))
+
+
+def test_dense_eig_rejects_bad_sizes(g):
+    with pytest.raises(Exception):
+        g.dense_eig(dev(np.eye(4)), 5)
+    with pytest.raises(Exception):
+        g.dense_eig(dev(np.eye(1025)), 10)
