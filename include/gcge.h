@@ -127,7 +127,7 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "profile"      [0]     time the launches of the main kernel classes with HIP events
  *                         (fields prof_* of gcge_stats)
  *  "dense_eig"    [1]     small Rayleigh-Ritz eigenproblem on the device (gcge_dense_eig)
- *                         when its order is at most 1024; 0 solves it on the host
+ *                         when its order is at most 768; 0 solves it on the host
  *                         (gcge_small_eigh)
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
@@ -249,7 +249,7 @@ int gcge_small_eigh(int n, double *a, double *w, double *z, int nwant);
  * re-orthonormalization of the eigenvectors.  a: device n x n row-major
  * symmetric (lda, not modified); w: device double[nwant], the nwant smallest
  * eigenvalues ascending; x: device n x nwant row-major (ldx), the matching
- * orthonormal eigenvectors as columns.  1 <= nwant <= n <= 1024 (INVALID_ARG
+ * orthonormal eigenvectors as columns.  1 <= nwant <= n <= 768 (INVALID_ARG
  * otherwise).  Asynchronous on stream. */
 int gcge_dense_eig(int n, const double *a, int64_t lda, int nwant, double *w, double *x, int64_t ldx,
                    void *stream);

@@ -2,7 +2,8 @@
 // problem of STEP 3 (Section 3.2; the paper calls LAPACK dsyevx on the host).
 //
 //   1. Householder reduction of the n x n matrix to tridiagonal form T by one
-//      work-group (the matrix stays in L2; vectors in LDS).
+//      work-group, one pass over the lower triangle per step (the matrix
+//      stays in L2; vectors in LDS).
 //   2. The nwant smallest eigenvalues of T by multisection: one wave per
 //      eigenvalue, 64 Sturm counts per round (one per lane).
 //   3. Their eigenvectors by inverse iteration with a partially pivoted LU of
@@ -61,79 +62,197 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. Householder tridiagonalization, one work-group of 1024 threads.
-// a: n x n symmetric, row-major (lda).  Step k reflects rows/columns k+1..n-1
-// with H_k = I - tau_k v v^T (v[0] = 1) chosen from row k; v is stored over
-// row k (columns k+1..n-1) for the back-transformation.  d, e: diagonal and
-// off-diagonal of T; tau[k] for k < n-2.
+// 1. Householder tridiagonalization, one work-group of 1024 threads (16
+// waves).  a: n x n symmetric, row-major (lda); only its lower triangle is
+// read after the first row.  Reflector k (H_k = I - tau_k v v^T, v[0] = 1)
+// is chosen from column k below the diagonal and stored over row k, columns
+// k+1..n-1 (the upper triangle, otherwise unused) for the back-transformation.
+//
+// Each step makes one pass over the lower triangle of the trailing block: it
+// applies the pending rank-2 update of the previous reflector (B -= v w^T +
+// w v^T) and, in the same pass, accumulates the product of the updated block
+// with the next reflector (row sums, plus column contributions kept per lane
+// in registers and added across waves in a fixed order).  The next reflector
+// itself comes from the updated first column, computed just before the pass.
+// d, e: diagonal and off-diagonal of T; tau[k] for k < n-2.
 // ---------------------------------------------------------------------------
 constexpr int TRI_T = 1024, TRI_W = TRI_T / 64;
+static_assert(DENSE_EIG_MAX <= 12 * 64, "k_tridiag instances cover 12 column slots per lane");
 
+// y = C v over the trailing block C = rows/cols r0..n-1, first applying the
+// pending update C -= sv sw^T + sw sv^T when UPD.  y goes to sy[r0..n-1].
+// A wave takes four consecutive rows at a time (all their loads in flight
+// together); lane l holds columns l, l + 64, ... (NS slots).
+template <bool UPD, int NS>
+__device__ __forceinline__ void tri_pass(int n, double *__restrict__ a, int64_t lda, int r0,
+                                         const double *sv, const double *sw, const double *vn, double *sy,
+                                         double *comb) {
+    constexpr int RU = 2;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int mm = n - r0;
+    double part[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) part[t] = 0.0;
+    for (int rb = wave * RU; rb < mm; rb += TRI_W * RU) {
+        double acc[RU], vi[RU], wi[RU], vni[RU];
+        const double *rows[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int i = min(r0 + rb + u, n - 1);
+            acc[u] = 0.0;
+            vi[u] = UPD ? sv[i] : 0.0;
+            wi[u] = UPD ? sw[i] : 0.0;
+            vni[u] = vn[i];
+            rows[u] = a + (int64_t)i * lda + r0;
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int r = lane + 64 * t;
+            const int rc = min(r, mm - 1);
+            double x[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) x[u] = (rb + u < mm && r <= rb + u) ? rows[u][rc] : 0.0;
+            const double swr = UPD ? sw[r0 + rc] : 0.0, svr = UPD ? sv[r0 + rc] : 0.0, vnr = vn[r0 + rc];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int ri = rb + u;
+                if (ri < mm && r <= ri) {
+                    double xv = x[u];
+                    if (UPD) {
+                        xv -= vi[u] * swr + wi[u] * svr;
+                        const_cast<double *>(rows[u])[r] = xv;
+                    }
+                    acc[u] += xv * vnr;
+                    if (r < ri) part[t] += xv * vni[u];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const double s = wsum(acc[u]);
+            if (lane == 0 && rb + u < mm) sy[r0 + rb + u] = s;
+        }
+    }
+    __syncthreads();
+    // column contributions: comb[q] = part of wave q + 12, + wave q + 8, + wave q + 4, + wave q
+    for (int stage = 3; stage >= 0; --stage) {
+        if (wave / 4 == stage) {
+            double *c = comb + (int64_t)(wave % 4) * n;
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const int r = lane + 64 * t;
+                if (r < mm) c[r] = (stage == 3) ? part[t] : c[r] + part[t];
+            }
+        }
+        __syncthreads();
+    }
+    for (int r = tid; r < mm; r += TRI_T) {
+        double y = sy[r0 + r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y += comb[(int64_t)q * n + r];
+        sy[r0 + r] = y;
+    }
+    __syncthreads();
+}
+
+// Reflector from x[r0..n-1] (x[r0] = alpha): v -> sv2[r0..n-1], returns
+// (tau, beta).  Identical in every thread.
+__device__ __forceinline__ void tri_reflector(int n, int r0, const double *x, double *sv2, double *red,
+                                              double &tau_out, double &beta_out) {
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int i = r0 + 1 + tid; i < n; i += TRI_T) s += x[i] * x[i];
+    s = block_sum<TRI_W>(s, red);
+    const double alpha = x[r0];
+    if (s == 0.0) {
+        for (int i = r0 + tid; i < n; i += TRI_T) sv2[i] = (i == r0) ? 1.0 : 0.0;
+        tau_out = 0.0;
+        beta_out = alpha;
+    } else {
+        const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        const double sc = 1.0 / (alpha - beta);
+        for (int i = r0 + tid; i < n; i += TRI_T) sv2[i] = (i == r0) ? 1.0 : x[i] * sc;
+        tau_out = (beta - alpha) / beta;
+        beta_out = beta;
+    }
+    __syncthreads();
+}
+
+// w = p + K v with p = tau y, K = -tau/2 p.v over r0..n-1
+__device__ __forceinline__ void tri_w(int n, int r0, double t, const double *sy, const double *sv2, double *sw2,
+                                      double *red) {
+    const int tid = threadIdx.x;
+    double pv = 0.0;
+    for (int i = r0 + tid; i < n; i += TRI_T) pv += t * sy[i] * sv2[i];
+    pv = block_sum<TRI_W>(pv, red);
+    const double K = -0.5 * t * pv;
+    for (int i = r0 + tid; i < n; i += TRI_T) sw2[i] = t * sy[i] + K * sv2[i];
+    __syncthreads();
+}
+
+template <int NS>
 __global__ __launch_bounds__(TRI_T) void k_tridiag(int n, double *__restrict__ a, int64_t lda,
                                                     double *__restrict__ d, double *__restrict__ e,
                                                     double *__restrict__ tau) {
     extern __shared__ double sm[];
-    double *v = sm, *p = sm + n;
+    double *svA = sm, *swA = sm + n, *svB = sm + 2 * n, *swB = sm + 3 * n, *sy = sm + 4 * n, *sx = sm + 5 * n;
+    double *comb = sm + 6 * n;   // 4 x n
     __shared__ double red[TRI_W];
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        double *x = a + (int64_t)k * lda + (k + 1);
-        double s = 0.0;
-        for (int i = 1 + tid; i < m; i += TRI_T) s += x[i] * x[i];
-        s = block_sum<TRI_W>(s, red);
-        const double alpha = x[0];
-        if (s == 0.0) {
-            if (tid == 0) {
-                tau[k] = 0.0;
-                e[k] = alpha;
-                d[k] = a[(int64_t)k * lda + k];
-            }
-            __syncthreads();
-            continue;
-        }
-        const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
-        const double t = (beta - alpha) / beta;
-        const double sc = 1.0 / (alpha - beta);
-        for (int i = tid; i < m; i += TRI_T) v[i] = (i == 0) ? 1.0 : x[i] * sc;
-        __syncthreads();
-        for (int i = tid; i < m; i += TRI_T) x[i] = v[i];
+    const int tid = threadIdx.x;
+    if (n <= 2) {
         if (tid == 0) {
-            tau[k] = t;
-            e[k] = beta;
-            d[k] = a[(int64_t)k * lda + k];
+            d[0] = a[0];
+            if (n == 2) {
+                e[0] = a[lda];
+                d[1] = a[lda + 1];
+                tau[0] = 0.0;
+            }
         }
-        double *A22 = a + (int64_t)(k + 1) * lda + (k + 1);
-        // p = t A22 v, one wave per row
-        for (int i = wave; i < m; i += TRI_W) {
-            const double *row = A22 + (int64_t)i * lda;
-            double acc = 0.0;
-            for (int j = lane; j < m; j += 64) acc += row[j] * v[j];
-            acc = wsum(acc);
-            if (lane == 0) p[i] = t * acc;
-        }
-        __syncthreads();
-        double pv = 0.0;
-        for (int i = tid; i < m; i += TRI_T) pv += p[i] * v[i];
-        pv = block_sum<TRI_W>(pv, red);
-        const double K = -0.5 * t * pv;
-        for (int i = tid; i < m; i += TRI_T) p[i] += K * v[i];   // p now holds w
-        __syncthreads();
-        // A22 -= v w^T + w v^T
-        for (int i = wave; i < m; i += TRI_W) {
-            double *row = A22 + (int64_t)i * lda;
-            const double vi = v[i], wi = p[i];
-            for (int j = lane; j < m; j += 64) row[j] -= vi * p[j] + wi * v[j];
-        }
-        __syncthreads();
+        return;
     }
+    // reflector 0 from row 0 (the input is fully symmetric)
+    for (int i = 1 + tid; i < n; i += TRI_T) sx[i] = a[i];
+    __syncthreads();
+    double t0, b0;
+    tri_reflector(n, 1, sx, svA, red, t0, b0);
+    for (int i = 1 + tid; i < n; i += TRI_T) a[i] = svA[i];
     if (tid == 0) {
-        if (n >= 2) {
-            d[n - 2] = a[(int64_t)(n - 2) * lda + (n - 2)];
-            e[n - 2] = a[(int64_t)(n - 2) * lda + (n - 1)];
-            tau[n - 2] = 0.0;
+        d[0] = a[0];
+        e[0] = b0;
+        tau[0] = t0;
+    }
+    tri_pass<false, NS>(n, a, lda, 1, nullptr, nullptr, svA, sy, comb);
+    tri_w(n, 1, t0, sy, svA, swA, red);
+    double *sv = svA, *sw = swA, *sv2 = svB, *sw2 = swB;
+    for (int k = 0; k + 4 <= n; ++k) {
+        const int k1 = k + 1;
+        // updated column k1 below the diagonal and the diagonal entry
+        for (int i = k1 + 1 + tid; i < n; i += TRI_T)
+            sx[i] = a[(int64_t)i * lda + k1] - (sv[i] * sw[k1] + sw[i] * sv[k1]);
+        if (tid == 0) d[k1] = a[(int64_t)k1 * lda + k1] - (sv[k1] * sw[k1] + sw[k1] * sv[k1]);
+        __syncthreads();
+        double t1, b1;
+        tri_reflector(n, k1 + 1, sx, sv2, red, t1, b1);
+        for (int i = k1 + 1 + tid; i < n; i += TRI_T) a[(int64_t)k1 * lda + i] = sv2[i];
+        if (tid == 0) {
+            e[k1] = b1;
+            tau[k1] = t1;
         }
-        d[n - 1] = a[(int64_t)(n - 1) * lda + (n - 1)];
+        tri_pass<true, NS>(n, a, lda, k1 + 1, sv, sw, sv2, sy, comb);
+        tri_w(n, k1 + 1, t1, sy, sv2, sw2, red);
+        double *tv = sv, *tw = sw;
+        sv = sv2;
+        sw = sw2;
+        sv2 = tv;
+        sw2 = tw;
+    }
+    // pending update of the last reflector on the trailing 2 x 2 block
+    if (tid == 0) {
+        const int p = n - 2, q = n - 1;
+        d[p] = a[(int64_t)p * lda + p] - (sv[p] * sw[p] + sw[p] * sv[p]);
+        e[p] = a[(int64_t)q * lda + p] - (sv[q] * sw[p] + sw[q] * sv[p]);
+        d[q] = a[(int64_t)q * lda + q] - (sv[q] * sw[q] + sw[q] * sv[q]);
+        tau[p] = 0.0;
     }
 }
 
@@ -421,8 +540,15 @@ hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, 
     e = hipMemcpy2DAsync(a, sizeof(double) * n, A, sizeof(double) * lda, sizeof(double) * n, n,
                          hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TRI_T), sizeof(double) * 2 * n, st, n, a, (int64_t)n, dg, off,
-                       tau);
+    {
+        const int ns = (n + 63) / 64;   // column slots per lane
+        const size_t lds = sizeof(double) * 10 * n;
+#define GCGE_TRI(NSv) \
+    if (ns == NSv) hipLaunchKernelGGL((k_tridiag<NSv>), dim3(1), dim3(TRI_T), lds, st, n, a, (int64_t)n, dg, off, tau);
+        GCGE_TRI(1) GCGE_TRI(2) GCGE_TRI(3) GCGE_TRI(4) GCGE_TRI(5) GCGE_TRI(6)
+        GCGE_TRI(7) GCGE_TRI(8) GCGE_TRI(9) GCGE_TRI(10) GCGE_TRI(11) GCGE_TRI(12)
+#undef GCGE_TRI
+    }
     hipLaunchKernelGGL(k_bisect, dim3(nwant), dim3(64), sizeof(double) * 2 * n, st, n, dg, off, nwant, w);
     const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n + 64;
     hipLaunchKernelGGL(k_invit, dim3(nwant), dim3(64), inv_lds, st, n, dg, off, nwant, w, 1e-10, Z, (int64_t)n);

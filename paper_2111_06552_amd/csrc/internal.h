@@ -35,14 +35,22 @@ struct Segs {
     }
 };
 
-// Sparse matrix in CSR form on the device (int32 indices).
+// Sparse matrix in CSR form on the device (int32 indices).  uorder, when not
+// null, is the order in which the SpMM visits the 64-row units of the matrix
+// (a permutation of 0 .. ceil(n/64)-1; the data stay in natural order).
 template <typename T>
 struct DevCsr {
     int64_t n = 0, nnz = 0;
     const int32_t *rowptr = nullptr;
     const int32_t *colind = nullptr;
     const T *val = nullptr;
+    const int32_t *uorder = nullptr;
 };
+
+// SpMM traversal order of 64-row units for a pattern (rowptr/colind on the
+// host), or an empty vector when natural order is kept.  *plane receives the
+// detected coupling distance (0 if none).
+std::vector<int32_t> spmm_unit_order(int64_t n, const int32_t *rowptr, const int32_t *colind, int64_t *plane);
 
 // Grow-only device scratch used by the reductions.
 struct Workspace {
@@ -149,7 +157,7 @@ hipError_t diag_grad(int64_t n, const double *X, int64_t ldx, int nev, const dou
 
 // ------------------------------------------------------------ device dense
 // Largest matrix order of the device eigensolver (LDS per work-group).
-constexpr int DENSE_EIG_MAX = 1024;
+constexpr int DENSE_EIG_MAX = 768;
 
 // Grow-only device scratch of dense_eig.
 struct DenseEigWork {

@@ -54,6 +54,26 @@ __device__ __forceinline__ RowWalk row_walk(int64_t n, int ng) {
     return RowWalk{r0 + (int64_t)w * ng, r1, (int64_t)nw * ng};
 }
 
+// Row blocks of the SpMM over a unit order: the logical row space of
+// ceil(n/64) 64-row units is split into one contiguous range of whole units
+// per XCD and walked like row_walk in blocks of ng rows (ng divides 64);
+// logical row l is physical row uorder[l / 64] * 64 + l % 64 (identity when
+// uorder is null).
+__device__ __forceinline__ RowWalk unit_walk(int64_t n, int ng) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nx = nb < NXCD ? nb : NXCD;
+    const int x = b % nx, w = b / nx;
+    const int nw = nb / nx + (x < nb % nx ? 1 : 0);
+    const int64_t nu = (n + 63) / 64;
+    const int64_t per = (nu + nx - 1) / nx * 64;
+    const int64_t nl = nu * 64;
+    const int64_t r0 = min(nl, (int64_t)x * per), r1 = min(nl, r0 + per);
+    return RowWalk{r0 + (int64_t)w * ng, r1, (int64_t)nw * ng};
+}
+__device__ __forceinline__ int64_t unit_row(const int32_t *uorder, int64_t l) {
+    return uorder != nullptr ? (int64_t)uorder[l >> 6] * 64 + (l & 63) : l;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -339,10 +359,10 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                                                const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
                                                int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
                                                int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
-                                               const int *__restrict__ skip) {
+                                               const int *__restrict__ skip, const int32_t *__restrict__ uorder) {
     if (skip != nullptr && skip[0] == 0) return;
     constexpr int NG = 256 / G, U = 8;
-    constexpr int RS = NG > 32 ? NG : 32;   // rows per staged block
+    constexpr int RS = NG > 32 ? NG : 32;   // rows per staged block (divides 64)
     constexpr int RPG = RS / NG;            // rows per group per block
     constexpr int CAP = 1024;               // staged nonzeros per block
     __shared__ int s_rp[RS + 1];
@@ -351,7 +371,7 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
     __shared__ T s_vb[MODE == 2 ? CAP : 1];
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
     const int chunk = blockIdx.x;
-    const RowWalk rw = row_walk(n, RS);
+    const RowWalk rw = unit_walk(n, RS);
     const int c0 = lig * V;
     const bool on = c0 < k;
     const int c0l = on ? c0 : 0;   // load column (lanes past k read column 0)
@@ -361,8 +381,10 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
         sg[v] = (MODE != 0 && c0 + v < k) ? sigma[c0 + v] : T(0);
         red1[v] = red2[v] = T(0);
     }
-    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
-        const int nrows = (int)min((int64_t)RS, rw.end - base);
+    for (int64_t lb = rw.first; lb < rw.end; lb += rw.stride) {
+        const int64_t base = unit_row(uorder, lb);
+        const int nrows = (int)min((int64_t)RS, n - base);
+        if (nrows <= 0) continue;   // past the last row (uniform over the work-group)
         for (int t = tid; t <= nrows; t += 256) s_rp[t] = rowptr[base + t];
         __syncthreads();
         const int eb = s_rp[0], ne = s_rp[nrows] - eb;
@@ -510,14 +532,15 @@ static hipError_t spmm_dispatch(const DevCsr<T> &A, const T *vb, const T *dg, co
         const int lanes = (k + V - 1) / V;
         const int G = lanes <= 4 ? 4 : lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
         const int RS = std::max(256 / G, 32);
-        units = (int)std::min<int64_t>((A.n + RS - 1) / RS, 1 << 30);
+        units = (int)std::min<int64_t>((A.n + 63) / 64 * (64 / RS), 1 << 30);
 #define GCGE_SPMMS(Gv)                                                                                   \
     if (G == Gv) {                                                                                       \
         fn = (const void *)k_spmms<T, Gv, V, MODE, RED>;                                                 \
         const int g = resident_grid(fn, units);                                                          \
         if (nparts) *nparts = g;                                                                         \
         hipLaunchKernelGGL((k_spmms<T, Gv, V, MODE, RED>), dim3(g), block, 0, st, A.n, A.rowptr, A.colind, \
-                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip);     \
+                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip,      \
+                           A.uorder);                                                                   \
     }
         GCGE_SPMMS(4) else GCGE_SPMMS(8) else GCGE_SPMMS(16) else GCGE_SPMMS(32) else GCGE_SPMMS(64)
 #undef GCGE_SPMMS

@@ -4,6 +4,7 @@
 #include "operator.h"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -72,6 +73,56 @@ void Stager::release() {
     if (ring) (void)hipHostFree(ring);
     ring = nullptr;
     cap = off = 0;
+}
+
+// ---------------------------------------------------------- SpMM unit order
+// Operators of grids in natural order couple most rows to a row a fixed
+// distance S ahead (the next plane).  Swept in natural order, the vector rows
+// one plane back have left the 4 MB L2 of an XCD before they are gathered
+// again, so every vector row is fetched about three times.  When such an S
+// exists, each XCD's contiguous range of 64-row units is visited by blocks of
+// positions within a plane, plane after plane: units whose (row mod S) falls
+// in the same block of SPMM_BX rows come together, so a row's neighbours in
+// the adjacent planes were gathered a few thousand rows earlier.  Only the
+// visiting order changes; products are identical to natural order.
+constexpr int64_t SPMM_BX = 1024;   // rows of a block within a plane
+constexpr int SPMM_XCD = 8;
+
+std::vector<int32_t> spmm_unit_order(int64_t n, const int32_t *rp, const int32_t *ci, int64_t *plane) {
+    *plane = 0;
+    const int64_t nu = (n + 63) / 64;
+    if (n < 4 * 256) return {};
+    // the largest forward offset beyond 64 rows that half of the sampled rows have
+    const int64_t step = std::max<int64_t>(1, n / 20000);
+    std::map<int64_t, int64_t> cnt;
+    int64_t samples = 0;
+    for (int64_t r = 0; r < n; r += step) {
+        ++samples;
+        for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+            const int64_t off = (int64_t)ci[e] - r;
+            if (off > 64) ++cnt[off];
+        }
+    }
+    int64_t S = 0;
+    for (const auto &kv : cnt)
+        if (2 * kv.second >= samples) S = std::max(S, kv.first);
+    if (S < 256 || n < 4 * S) return {};
+    *plane = S;
+    std::vector<int32_t> order(nu);
+    const int64_t per = (nu + SPMM_XCD - 1) / SPMM_XCD;
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int32_t>> keys;
+    for (int64_t u0 = 0; u0 < nu; u0 += per) {
+        const int64_t u1 = std::min(nu, u0 + per);
+        keys.clear();
+        for (int64_t u = u0; u < u1; ++u) {
+            const int64_t row = u * 64;
+            keys.push_back({{(row % S) / SPMM_BX, row / S}, (int32_t)u});
+        }
+        std::stable_sort(keys.begin(), keys.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (int64_t j = 0; j < u1 - u0; ++j) order[u0 + j] = keys[j].second;
+    }
+    return order;
 }
 
 // ---------------------------------------------------------------- Operator
@@ -180,6 +231,13 @@ int Operator::build(const gcge_csr *A, int b_kind, const void *B, hipStream_t st
         GCGE_HIP(hipMalloc((void **)&dpos, sizeof(int32_t) * n));
         GCGE_HIP(hipMemcpy(dpos, dp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     }
+    {
+        const std::vector<int32_t> uo = spmm_unit_order(n, urp.data(), uci.data(), &plane);
+        if (!uo.empty()) {
+            GCGE_HIP(hipMalloc((void **)&uorder, sizeof(int32_t) * uo.size()));
+            GCGE_HIP(hipMemcpy(uorder, uo.data(), sizeof(int32_t) * uo.size(), hipMemcpyHostToDevice));
+        }
+    }
     GCGE_HIP(hipMalloc((void **)&a, sizeof(double) * std::max<int64_t>(nnz, 1)));
     if (Bc) GCGE_HIP(hipMalloc((void **)&b, sizeof(double) * std::max<int64_t>(nnz, 1)));
     if (b_kind == GCGE_B_DIAG) GCGE_HIP(hipMalloc((void **)&dg, sizeof(double) * n));
@@ -214,9 +272,11 @@ int Operator::set_values(const double *a_val, const void *b_val, hipStream_t st,
 }
 
 void Operator::destroy() {
-    int32_t *ip[] = {rowptr, colind, dpos, mapA, mapB};
+    int32_t *ip[] = {rowptr, colind, dpos, mapA, mapB, uorder};
     for (auto p : ip)
         if (p) (void)hipFree(p);
+    uorder = nullptr;
+    plane = 0;
     double *dp[] = {a, b, dg};
     for (auto p : dp)
         if (p) (void)hipFree(p);

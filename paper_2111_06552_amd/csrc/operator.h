@@ -42,6 +42,8 @@ struct Operator {
     // host copies of the user patterns' position maps into the union pattern
     int32_t *mapA = nullptr, *mapB = nullptr;       // device int32[nnzA], [nnzB]
     bool same_pattern = true;                       // union pattern == A's pattern (and B's for CSR)
+    int32_t *uorder = nullptr;                      // SpMM unit order (device) or null
+    int64_t plane = 0;                              // coupling distance behind the order
 
     // Build from user (device) arrays.  Returns a GCGE status; err gets a message.
     int build(const gcge_csr *A, int b_kind, const void *B, hipStream_t st, std::string &err);
@@ -49,12 +51,14 @@ struct Operator {
     int set_values(const double *a_val, const void *b_val, hipStream_t st, std::string &err);
     void destroy();
 
-    DevCsr<double> A_csr() const { return DevCsr<double>{n, nnz, rowptr, colind, a}; }
+    DevCsr<double> A_csr() const { return DevCsr<double>{n, nnz, rowptr, colind, a, uorder}; }
+    template <typename T>
+    DevCsr<T> csr_of(const T *val) const { return DevCsr<T>{n, nnz, rowptr, colind, val, uorder}; }
     BOp bop() const {
         BOp o;
         o.kind = bkind;
         o.dg = dg;
-        o.csr = DevCsr<double>{n, nnz, rowptr, colind, b};
+        o.csr = DevCsr<double>{n, nnz, rowptr, colind, b, uorder};
         return o;
     }
     // m = A - theta B on the union pattern, and m32 = float(m) when m32 != nullptr.

@@ -394,7 +394,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
         CgState<double> cs{(double *)cm, (double *)(cm + slot), (double *)(cm + 2 * slot), (double *)(cm + 3 * slot),
                            (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
         CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
-        DevCsr<double> M{op.n, op.nnz, op.rowptr, op.colind, mval};
+        DevCsr<double> M = op.csr_of(mval);
         return runner.run(M, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
                           cg_its);
     }
@@ -413,7 +413,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
     CgState<float> cs{(float *)cm, (float *)(cm + slot), (float *)(cm + 2 * slot), (float *)(cm + 3 * slot),
                       (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
     CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
-    DevCsr<float> M{op.n, op.nnz, op.rowptr, op.colind, mval32};
+    DevCsr<float> M = op.csr_of(mval32);
     int rc = runner.run(M, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
                         cg_its);
     if (rc) return rc;
@@ -1120,7 +1120,7 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
                                    (double *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                    (int *)(c8 + 6 * slot)};
                 CgRunner<double> runner{n, C.ws, st, nullptr, nullptr, err};
-                DevCsr<double> M{n, op.nnz, op.rowptr, op.colind, m64};
+                DevCsr<double> M = op.csr_of(m64);
                 rc = runner.run(M, R, ldr, nullptr, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld, v + 3 * n * ld, ld, cs,
                                 nullptr);
                 if (!rc) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
@@ -1151,7 +1151,7 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
                                       (float *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                       (int *)(c8 + 6 * slot)};
                     CgRunner<float> runner{n, C.ws, st, nullptr, nullptr, err};
-                    DevCsr<float> M{n, op.nnz, op.rowptr, op.colind, m32};
+                    DevCsr<float> M = op.csr_of(m32);
                     rc = runner.run(M, R, ldr, dsc, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld, v + 3 * n * ld,
                                     ld, cs, nullptr);
                     if (!rc) e = copy_cols<float, double>(n, k, v, ld, delta, ldd, dusc, st);

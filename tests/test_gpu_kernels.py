@@ -171,6 +171,20 @@ def test_cg_fp64_block_widths(g, k):
     assert np.max(np.abs(host(D) - ref)) < 1e-10 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cg_plane_blocked_spmm_order(g, precision):
+    """A 48^3 grid couples rows 2304 apart: the operator's SpMM visits row
+    blocks plane by plane within blocks of positions; the products (and so the
+    CG iterates) must equal natural order's."""
+    A = wl.laplace3d_7pt(48)
+    d = wl.diag_uniform(A.n)
+    R = RNG.standard_normal((A.n, 8))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), dev(d), 40.0, dev(R), maxit=3, rel_tol=0.0, precision=precision)
+    ref, _ = orc.cg_columnwise(A, "diag", d, 40.0, R, maxit=3, rel_tol=0.0)
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert np.max(np.abs(host(D) - ref)) < tol * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("k", [13, 50, 100])
 def test_cg_mixed_block_widths(g, k):
     A = wl.laplace3d_7pt(11)
@@ -270,7 +284,8 @@ def _check_dense_eig(g, A, nwant, ref=None):
     return w, X
 
 
-@pytest.mark.parametrize("n,nwant", [(1, 1), (2, 2), (3, 2), (17, 17), (64, 40), (200, 150), (450, 350)])
+@pytest.mark.parametrize("n,nwant", [(1, 1), (2, 2), (3, 2), (4, 4), (5, 3), (17, 17), (64, 40), (65, 65), (200, 150),
+                                     (450, 350), (768, 500)])
 def test_dense_eig_random_symmetric(g, n, nwant):
     M = RNG.standard_normal((n, n))
     A = (M + M.T) * 10.0
@@ -330,4 +345,4 @@ def test_dense_eig_rejects_bad_sizes(g):
     with pytest.raises(Exception):
         g.dense_eig(dev(np.eye(4)), 5)
     with pytest.raises(Exception):
-        g.dense_eig(dev(np.eye(1025)), 10)
+        g.dense_eig(dev(np.eye(769)), 10)
