@@ -1393,9 +1393,8 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
 }
 
 // ---------------------------------------------------------------------------
-// Y = alpha * X S + beta * Y on the FP64 matrix cores: 64 x 64 output tiles,
-// 4 waves of 32 x 32 each, the X and S tiles staged through LDS in K-chunks of
-// 16 columns.  X is read as up to MAX_SEG column segments.
+// Y = alpha * X S + beta * Y on the FP64 matrix cores, X read as up to
+// MAX_SEG column segments, X and S tiles staged through LDS.
 // ---------------------------------------------------------------------------
 struct GemmParams {
     int64_t n;
@@ -1411,13 +1410,17 @@ struct GemmParams {
     int nct;
 };
 
-template <int BN>
-__global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
-    // BM x BN output tile per work-group, 4 waves as 2 x 2 of (BM/2) x (BN/2);
-    // K walked in chunks of BK columns across the X segments.  The next
-    // chunk's global loads are held in registers while the MFMAs consume the
-    // current chunk from LDS.
-    constexpr int BM = 128, BK = 16, MB = BM / 32, NB = BN / 32, SPT = BK * BN / 256;
+// BM x BN output tile per work-group, WM x WN waves of (BM/WM) x (BN/WN);
+// K walked in chunks of BK columns, segment by segment.  The next chunk's
+// global loads are held in registers (clamped addresses, masked values, no
+// branches) while the MFMAs consume the current chunk from LDS.
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmParams P) {
+    constexpr int T = 64 * WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN, MB = TM / 16, NB = TN / 16;
+    constexpr int VPT = BM * BK / T, SPT = BK * BN / T;
+    constexpr int VRS = T / BK, SRS = T / BN;
+    static_assert(VPT * T == BM * BK && SPT * T == BK * BN, "tile / thread mismatch");
     __shared__ double Vt[BM][BK + 1];
     __shared__ double St[BK][BN];
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -1425,42 +1428,39 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
     const int64_t row0 = (int64_t)rt * BM;
     const int col0 = ct * BN;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
-    const int wr = wave / 2, wc = wave % 2;
+    const int wr = wave / WN, wc = wave % WN;
     d4 acc[MB][NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    // staging registers, lane-contiguous: V column tid % BK of rows tid / BK +
-    // 16 q; S column tid % BN of rows tid / BN + (256 / BN) q
-    constexpr int SRS = 256 / BN;
     const int vc = tid % BK, vr = tid / BK;
     const int sc = tid % BN, sr = tid / BN;
-    double vreg[8], sreg[SPT];
-    // clamped addresses, masked values: no branches around the loads
+    const bool scv = col0 + sc < P.k;
+    const int64_t rmax = P.n - 1;
+    double vreg[VPT], sreg[SPT];
     auto load_chunk = [&](int sgi, int kc) {
-        const Seg sg = P.s[sgi];
-        const bool cv = kc + vc < sg.ncol;
-        const double *vb = sg.p + (cv ? kc + vc : 0);
-        double vv[8];
+        const double *xp = P.s[sgi].p;
+        const int64_t xld = P.s[sgi].ld;
+        const int ncol = P.s[sgi].ncol;
+        const bool cv = kc + vc < ncol;
+        const double *vb = xp + (cv ? kc + vc : 0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) vv[q] = vb[min(row0 + vr + 16 * q, P.n - 1) * sg.ld];
+        for (int q = 0; q < VPT; ++q) vreg[q] = vb[min(row0 + vr + VRS * q, rmax) * xld];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) vreg[q] = (cv && row0 + vr + 16 * q < P.n) ? vv[q] : 0.0;
-        const bool scv = col0 + sc < P.k;
+        for (int q = 0; q < VPT; ++q) vreg[q] = (cv && row0 + vr + VRS * q <= rmax) ? vreg[q] : 0.0;
         const double *sb = P.S + (int64_t)P.soff[sgi] * P.lds + (scv ? col0 + sc : 0);
-        double sv[SPT];
 #pragma unroll
-        for (int q = 0; q < SPT; ++q) sv[q] = sb[(int64_t)min(kc + sr + SRS * q, sg.ncol - 1) * P.lds];
+        for (int q = 0; q < SPT; ++q) sreg[q] = sb[(int64_t)min(kc + sr + SRS * q, ncol - 1) * P.lds];
 #pragma unroll
-        for (int q = 0; q < SPT; ++q) sreg[q] = (scv && kc + sr + SRS * q < sg.ncol) ? sv[q] : 0.0;
+        for (int q = 0; q < SPT; ++q) sreg[q] = (scv && kc + sr + SRS * q < ncol) ? sreg[q] : 0.0;
     };
     int sgi = 0, kc = 0;
-    bool have = P.nseg > 0;
-    if (have) load_chunk(0, 0);
-    while (have) {
+    while (sgi < P.nseg && P.s[sgi].ncol <= 0) ++sgi;
+    if (sgi < P.nseg) load_chunk(sgi, 0);
+    while (sgi < P.nseg) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Vt[vr + 16 * q][vc] = vreg[q];
+        for (int q = 0; q < VPT; ++q) Vt[vr + VRS * q][vc] = vreg[q];
 #pragma unroll
         for (int q = 0; q < SPT; ++q) St[sr + SRS * q][sc] = sreg[q];
         __syncthreads();
@@ -1468,16 +1468,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
         if (nkc >= P.s[nsgi].ncol) {
             ++nsgi;
             nkc = 0;
+            while (nsgi < P.nseg && P.s[nsgi].ncol <= 0) ++nsgi;
         }
-        const bool nhave = nsgi < P.nseg;
-        if (nhave) load_chunk(nsgi, nkc);
+        if (nsgi < P.nseg) load_chunk(nsgi, nkc);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             double av[MB], bv[NB];
 #pragma unroll
-            for (int a = 0; a < MB; ++a) av[a] = Vt[wr * (BM / 2) + a * 16 + li][ks + lk];
+            for (int a = 0; a < MB; ++a) av[a] = Vt[wr * TM + a * 16 + li][ks + lk];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) bv[b] = St[ks + lk][wc * (BN / 2) + b * 16 + li];
+            for (int b = 0; b < NB; ++b) bv[b] = St[ks + lk][wc * TN + b * 16 + li];
 #pragma unroll
             for (int a = 0; a < MB; ++a)
 #pragma unroll
@@ -1487,28 +1487,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams P) {
         __syncthreads();
         sgi = nsgi;
         kc = nkc;
-        have = nhave;
     }
-    // epilogue: the beta * Y reads use clamped addresses (no per-element
-    // branches); stores are masked
+    // epilogue: Y = alpha acc + beta Y; stores masked
     const bool addy = P.beta != 0.0;
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int col = col0 + wc * (BN / 2) + b * 16 + li;
-            const int colc = min(col, P.k - 1);
-            double yv[4];
+            const int col = col0 + wc * TN + b * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = min(row0 + wr * (BM / 2) + a * 16 + lk + 4 * r, P.n - 1);
-                yv[r] = addy ? P.Y[row * P.ldy + colc] : 0.0;
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wr * (BM / 2) + a * 16 + lk + 4 * r;
-                const double v = fma(P.beta, yv[r], P.alpha * acc[a][b][r]);
-                if (row < P.n && col < P.k) P.Y[row * P.ldy + col] = v;
+                const int64_t row = row0 + wr * TM + a * 16 + lk + 4 * r;
+                if (row < P.n && col < P.k) {
+                    double *y = P.Y + row * P.ldy + col;
+                    *y = addy ? fma(P.beta, *y, P.alpha * acc[a][b][r]) : P.alpha * acc[a][b][r];
+                }
             }
         }
 }
@@ -1532,13 +1525,15 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
     P.beta = beta;
     P.Y = Y;
     P.ldy = ldy;
+    // up to 64 output columns: 128 x 64 tiles, K chunks of 32, 4 waves;
+    // wider: 128 x 128 tiles, K chunks of 16, 8 waves (4 x 2)
     const int BN = (k <= 64) ? 64 : 128;
     P.nct = (k + BN - 1) / BN;
     const int64_t nrt = (n + 127) / 128;
     const int64_t nb = nrt * P.nct;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    if (BN == 64) hipLaunchKernelGGL(k_gemm<64>, dim3((unsigned)nb), dim3(256), 0, st, P);
-    else hipLaunchKernelGGL(k_gemm<128>, dim3((unsigned)nb), dim3(256), 0, st, P);
+    if (BN == 64) hipLaunchKernelGGL((k_gemm<128, 64, 32, 2, 2>), dim3((unsigned)nb), dim3(256), 0, st, P);
+    else hipLaunchKernelGGL((k_gemm<128, 128, 16, 4, 2>), dim3((unsigned)nb), dim3(512), 0, st, P);
     return hipGetLastError();
 }
 
