@@ -98,7 +98,7 @@ int max_row_parts() { return num_cu() * 8; }
 // query, cached per kernel): row-streaming kernels are launched with exactly
 // that many work-groups (capped by the number of work units), so all of them
 // run in one wave of residency and finish together.
-static int resident_grid(const void *fn, int64_t units) {
+static int resident_grid(const void *fn, int64_t units, int block = 256) {
     static std::mutex mu;
     static std::unordered_map<const void *, int> cache;
     int nb = 0;
@@ -108,7 +108,7 @@ static int resident_grid(const void *fn, int64_t units) {
         if (it != cache.end()) {
             nb = it->second;
         } else {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 4;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0) != hipSuccess || nb < 1) nb = 4;
             nb = std::min(nb, 8);
             cache[fn] = nb;
         }
@@ -1256,24 +1256,27 @@ __global__ __launch_bounds__(1024) void k_tile_reduce(GramParams P, int TN, int 
 // registers while the MFMAs consume the current ones.  Each work-group writes
 // its partial tile; k_tile_reduce sums the partials.
 template <bool HAS_D>
-__global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
-    constexpr int T = 64, KR = 32;
-    __shared__ double Xs[KR][T];
-    __shared__ double Ys[KR][T];
+__global__ __launch_bounds__(512) void k_gram_lds(GramParams P) {
+    constexpr int T = 64, KR = 32, NT = 512;
+    __shared__ double sbuf[2 * KR * T];   // X and Y stages; at the end, one wave group's tile
+    double(*Xs)[T] = reinterpret_cast<double(*)[T]>(sbuf);
+    double(*Ys)[T] = reinterpret_cast<double(*)[T]>(sbuf + KR * T);
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int per_chunk = P.ntile * P.nyt;
     const int chunk = lid / per_chunk, rem = lid % per_chunk;
     const int ti = rem / P.nyt, yt = rem % P.nyt;
     const GTile tl = P.t[ti];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
-    const int wr = wave / 2, wc = wave % 2;
+    // waves 0-3 take rows 0-15 of each stage, waves 4-7 rows 16-31; within a
+    // group, 2 x 2 waves of 32 x 32
+    const int wk = wave / 4, wr = (wave % 4) / 2, wc = wave % 2;
     const int64_t r0 = (int64_t)chunk * P.rows_per, r1 = min(P.n, r0 + P.rows_per);
     d4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    // staging: thread t holds column t % 64 of rows t / 64 + 4 q (q = 0..7), so
+    // staging: thread t holds column t % 64 of rows t / 64 + 8 q (q = 0..3), so
     // each load instruction of a wave reads 64 consecutive doubles of one row.
     // Addresses are clamped to valid elements and the values masked, so the
     // loads carry no branches.
@@ -1281,19 +1284,20 @@ __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
     const bool xcv = lc < tl.ncol, ycv = yt * T + lc < P.k;
     const double *xbase = tl.xp + tl.xcol0 + (xcv ? lc : 0);
     const double *ybase = P.Y + yt * T + (ycv ? lc : 0);
-    double xr[8], yr[8];
+    constexpr int Q = KR * T / NT;
+    double xr[Q], yr[Q];
     auto load = [&](int64_t rb) {
-        double xv[8], yv[8], dv[8];
+        double xv[Q], yv[Q], dv[Q];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t row = min(rb + lr + 4 * q, r1 - 1);
+        for (int q = 0; q < Q; ++q) {
+            const int64_t row = min(rb + lr + 8 * q, r1 - 1);
             xv[q] = xbase[row * tl.ldx];
             yv[q] = ybase[row * P.ldy];
             dv[q] = HAS_D ? P.d[row] : 1.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const bool rv = rb + lr + 4 * q < r1;
+        for (int q = 0; q < Q; ++q) {
+            const bool rv = rb + lr + 8 * q < r1;
             xr[q] = (rv && xcv) ? xv[q] : 0.0;
             yr[q] = (rv && ycv) ? yv[q] * dv[q] : 0.0;
         }
@@ -1302,19 +1306,20 @@ __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
     if (rb < r1) load(rb);
     for (; rb < r1; rb += KR) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            Xs[lr + 4 * q][lc] = xr[q];
-            Ys[lr + 4 * q][lc] = yr[q];
+        for (int q = 0; q < Q; ++q) {
+            Xs[lr + 8 * q][lc] = xr[q];
+            Ys[lr + 8 * q][lc] = yr[q];
         }
         __syncthreads();
         load(rb + KR);   // past the chunk end: clamped addresses, masked to zero
 #pragma unroll
-        for (int ks = 0; ks < KR; ks += 4) {
+        for (int ks = 0; ks < KR / 2; ks += 4) {
+            const int kr = wk * (KR / 2) + ks + lk;
             double av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = Xs[ks + lk][wr * 32 + a * 16 + li];
+            for (int a = 0; a < 2; ++a) av[a] = Xs[kr][wr * 32 + a * 16 + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Ys[ks + lk][wc * 32 + b * 16 + li];
+            for (int b = 0; b < 2; ++b) bv[b] = Ys[kr][wc * 32 + b * 16 + li];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1323,6 +1328,18 @@ __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
         }
         __syncthreads();
     }
+    // the second row group's tile through LDS, added to the first's (fixed order)
+    if (wk == 1) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sbuf[(wr * 32 + a * 16 + lk + 4 * r) * T + wc * 32 + b * 16 + li] = acc[a][b][r];
+    }
+    __syncthreads();
+    if (wk == 1) return;
     double *dst = P.part + ((size_t)(ti * P.nyt + yt) * P.nchunk + chunk) * (T * T);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -1331,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_gram_lds(GramParams P) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = wr * 32 + a * 16 + lk + 4 * r, j = wc * 32 + b * 16 + li;
-                dst[i * T + j] = acc[a][b][r];
+                dst[i * T + j] = acc[a][b][r] + sbuf[i * T + j];
             }
 }
 
@@ -1363,7 +1380,7 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     P.d = d;
     const int tiles = P.ntile * P.nyt;
     // one residency wave of work-groups for the large-tile kernel
-    const int cap = lds ? resident_grid((const void *)k_gram_lds<false>, 1 << 30) : 2048;
+    const int cap = lds ? resident_grid((const void *)k_gram_lds<false>, 1 << 30, 512) : 2048;
     int nchunk = std::max(1, cap / tiles);
     nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (n + 255) / 256));
     int64_t rp = (n + nchunk - 1) / nchunk;
@@ -1376,8 +1393,8 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     P.part = ws.part;
     dim3 grid(tiles * nchunk), block(256);
     if (lds) {
-        if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, block, 0, st, P);
-        else hipLaunchKernelGGL(k_gram_lds<false>, grid, block, 0, st, P);
+        if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, dim3(512), 0, st, P);
+        else hipLaunchKernelGGL(k_gram_lds<false>, grid, dim3(512), 0, st, P);
         hipLaunchKernelGGL(k_tile_reduce, dim3(tiles * (TM * TN / 64)), dim3(1024), 0, st, P, TN, TM * TN, C, ldc);
         return hipGetLastError();
     }
