@@ -856,7 +856,8 @@ __global__ __launch_bounds__(256) void k_cg_update_r_pk(int64_t n, int ldv, int 
         al[e] = (act && c0 + e < k) ? cs.alpha[c0 + e] : T(0);
         acc[e] = T(0);
     }
-    const RowWalk rw = row_walk(n, RW * U);
+    // plain interleaved walk: no reuse across rows, so no XCD partition
+    const RowWalk rw{(int64_t)blockIdx.x * RW * U, n, (int64_t)gridDim.x * RW * U};
     if (act) {
         for (int64_t row0 = rw.first; row0 < rw.end; row0 += rw.stride) {
             Vec<T, V> qv[U], rv[U];
