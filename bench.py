@@ -79,7 +79,8 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         return {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": per_launch,
-                "avg_launch_ms": avg_ms, "launches": launches}
+                "avg_launch_ms": avg_ms, "launches": launches,
+                "avg_launch_ms_all_widths": p["ms"] / p["launches"], "launches_all_widths": p["launches"]}
     kern = {"rotation_gemm": "k_gemm (Ritz rotation V_u xhat)", "p_gemm": "k_gemm (P block V_u phat)",
             "gram": "k_gram_lds + k_tile_reduce (Gram products)"}[name]
     per_launch = 2.0 * n * k
@@ -137,7 +138,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic.json")
 
 def short_name(kernel_name):
     """'void gcge::k_x<double, 32, 2>(long, ...)' -> 'k_x<double, 32, 2>'."""
-    n = kernel_name.split("(")[0]
+    n = kernel_name.replace("(anonymous namespace)::", "").split("(")[0]
     for pre in ("void ", "gcge::"):
         n = n.replace(pre, "")
     return n.strip()
@@ -163,7 +164,9 @@ def summarize_trace(d, top=30):
 
 
 def pmc_means(d, counter):
-    """Mean counter value per dispatch and kernel of a rocprofv3 --pmc run (directory d)."""
+    """Median counter value per dispatch and kernel of a rocprofv3 --pmc run
+    (directory d); the median is the value of the most common launch shape
+    (for the CG kernels: launches over a full block)."""
     import csv
     import glob
     f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[-1]
@@ -171,10 +174,12 @@ def pmc_means(d, counter):
     for r in csv.DictReader(open(f)):
         if r["Counter_Name"] != counter:
             continue
-        v = acc.setdefault(short_name(r["Kernel_Name"]), [0.0, 0])
-        v[0] += float(r["Counter_Value"])
-        v[1] += 1
-    return {k: v[0] / v[1] for k, v in acc.items()}
+        acc.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    out = {}
+    for k, v in acc.items():
+        v.sort()
+        out[k] = v[len(v) // 2]
+    return out
 
 
 def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
