@@ -412,8 +412,9 @@ def modified_block_orth(X, X0, bkind, B, b=None, tol=1e-13, max_pass=3, drop_tol
     X0 from X (repeated), then for blocks X_1..X_l of b columns: orthogonalize
     X_k by modified Gram-Schmidt, then deflate X_k from the later blocks
     (repeated).  b defaults to min(m/4, 200).  A column whose B-norm after
-    orthogonalization is at most drop_tol times its norm before is dependent
-    and is dropped (later columns move forward).  Returns (X_out, kept)."""
+    orthogonalization is at most drop_tol times its B-norm on entry (after the
+    X0 deflation) is linearly dependent and is dropped (later columns move
+    forward).  Returns (X_out, kept)."""
     X = np.array(X, dtype=np.float64)
     m = X.shape[1]
     if counters is None:
@@ -431,13 +432,16 @@ def modified_block_orth(X, X0, bkind, B, b=None, tol=1e-13, max_pass=3, drop_tol
     if b is None:
         b = max(1, min(m // 4, 200))
     cols = [X[:, j].copy() for j in range(m)]
+    # a column's B-norm on entry: the reference of the dependence test, so that a
+    # column reduced to rounding by the deflation of earlier blocks is dropped
+    norms_in = [np.sqrt(max(c @ apply_b(bkind, B, c), 0.0)) for c in cols]
     out = []
     k = 0
     while k < len(cols):
         blk = cols[k:k + b]
         kept_blk = []
-        for v in blk:
-            nrm0 = np.sqrt(v @ apply_b(bkind, B, v))
+        for jb, v in enumerate(blk):
+            nrm0 = norms_in[k + jb]
             for _ in range(2):
                 for u in kept_blk:
                     v = v - u * (u @ apply_b(bkind, B, v))

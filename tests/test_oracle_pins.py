@@ -456,3 +456,19 @@ def test_moving_memory_formula_weak_pin():
     full = orc.moving_memory(nev + 3 * bs, bs, nev + 5 * bs)
     assert moving == (3 * bs + 2 * bs) + 2 * (5 * bs) ** 2 + 10 * 5 * bs + 3 * bs * bs
     assert moving < full / 10
+
+
+def test_modified_block_orth_drops_columns_dependent_on_earlier_blocks():
+    """Algorithm 2 keeps one column per independent direction: a column equal
+    to a combination of columns in earlier blocks is reduced to rounding by
+    those blocks' deflations and must be dropped, like a duplicate inside a
+    block; the output spans the input."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((200, 24))
+    X[:, 5] = X[:, 2]                          # duplicate inside the first block
+    X[:, 17] = X[:, 1] - 2.0 * X[:, 9]         # dependent on the first two blocks
+    Xo, k = orc.modified_block_orth(X, None, "identity", None, b=6, drop_tol=1e-4)
+    assert k == 22
+    assert np.max(np.abs(Xo.T @ Xo - np.eye(k))) < 1e-13
+    proj = Xo @ (Xo.T @ X)
+    assert np.max(np.abs(proj - X)) < 1e-12 * np.max(np.abs(X))
