@@ -126,6 +126,9 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "check"        [1]     compute max_rel_residual and orth_error at the end
  *  "profile"      [0]     time the launches of the main kernel classes with HIP events
  *                         (fields prof_* of gcge_stats)
+ *  "orth"         [3]     STEP 2 orthogonalization: 3 RecursiveOrthSVD (Algorithm 3), 2 modified
+ *                         block orthogonalization (Algorithm 2, gcge_orth_mbo)
+ *  "orth_block"   [0]     block size of Algorithm 2 (0: min(m/4, 200), Section 3.1)
  *  "dense_eig"    [1]     small Rayleigh-Ritz eigenproblem on the device (gcge_dense_eig)
  *                         when its order is at most 768; 0 solves it on the host
  *                         (gcge_small_eigh)
@@ -234,6 +237,17 @@ int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double theta, const do
  * receives the number of output columns (host int). */
 int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq,
               double *W, int64_t ldw, int k, int *kept, void *stream);
+
+/* STEP 2 with the modified block orthogonalization of Algorithm 2 (Section
+ * 3.1) in place of Algorithm 3: after the same deflation against Q, the
+ * columns are taken in blocks of `block` (0: min(k/4, 200)); inside a block
+ * each column is B-orthogonalized against the block's kept columns by
+ * Gram-Schmidt (two passes) and normalized, or dropped when its squared
+ * B-norm falls to drop_tol (1e-8) of its value before; then the block is
+ * deflated from all later columns (repeated until the coefficients are
+ * small).  Arguments and results as gcge_orth. */
+int gcge_orth_mbo(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq,
+                  double *W, int64_t ldw, int k, int block, int *kept, void *stream);
 
 /* Host-only dense symmetric eigensolver used for the Rayleigh-Ritz problem
  * (the paper calls LAPACK dsyevx; this is the library's own Householder

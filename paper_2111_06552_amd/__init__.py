@@ -95,7 +95,7 @@ def _b_args(B):
 
 
 _INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
-             "dense_eig",
+             "dense_eig", "orth", "orth_block",
              "profile"}
 _DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol"}
 
@@ -341,8 +341,9 @@ def cg(A: DeviceCsr, B, theta: float, R: torch.Tensor, maxit: int = 30, rel_tol:
     return D, its
 
 
-def orth(W: torch.Tensor, Q: torch.Tensor | None = None, B=None):
-    """STEP 2: W B-orthogonalized against Q then by Algorithm 3; returns W[:, :kept]."""
+def orth(W: torch.Tensor, Q: torch.Tensor | None = None, B=None, algorithm: int = 3, block: int = 0):
+    """STEP 2: W B-orthogonalized against Q then by Algorithm 3 (or Algorithm 2
+    with blocks of `block` columns); returns W[:, :kept]."""
     _check_dev(W, torch.float64, "W")
     kept = ctypes.c_int(0)
     kind, bp, keep = _b_args(B)
@@ -353,8 +354,14 @@ def orth(W: torch.Tensor, Q: torch.Tensor | None = None, B=None):
         mq = Q.shape[1]
     else:
         pq, ldq, mq = None, 0, 0
-    _lib.check(_L().gcge_orth(W.shape[0], kind, bp, pq, ldq, mq, pw, ldw, W.shape[1], ctypes.byref(kept),
-                              ctypes.c_void_p(_stream(W.device))))
+    if algorithm == 3:
+        _lib.check(_L().gcge_orth(W.shape[0], kind, bp, pq, ldq, mq, pw, ldw, W.shape[1], ctypes.byref(kept),
+                                  ctypes.c_void_p(_stream(W.device))))
+    elif algorithm == 2:
+        _lib.check(_L().gcge_orth_mbo(W.shape[0], kind, bp, pq, ldq, mq, pw, ldw, W.shape[1], int(block),
+                                      ctypes.byref(kept), ctypes.c_void_p(_stream(W.device))))
+    else:
+        raise ValueError("algorithm must be 2 or 3")
     return W[:, :kept.value]
 
 

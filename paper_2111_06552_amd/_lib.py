@@ -26,7 +26,7 @@ EXPORTED = [
     "gcge_create", "gcge_set_option_i", "gcge_set_option_d", "gcge_set_stream", "gcge_set_initial_vectors",
     "gcge_solve", "gcge_update_values", "gcge_eig_grad", "gcge_destroy", "gcge_last_error", "gcge_spmm",
     "gcge_spmm_f32", "gcge_shifted_spmm", "gcge_residual", "gcge_gram", "gcge_gemm_update", "gcge_cg",
-    "gcge_orth", "gcge_small_eigh", "gcge_dense_eig", "gcge_p_hat", "gcge_pattern_grad",
+    "gcge_orth", "gcge_orth_mbo", "gcge_small_eigh", "gcge_dense_eig", "gcge_p_hat", "gcge_pattern_grad",
 ]
 
 
@@ -106,6 +106,8 @@ def load():
                                 c_void_p, c_int64, c_void_p, c_void_p]),
             "gcge_orth": (c_int, [c_int64, c_int, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int64, c_int,
                                   c_void_p, c_void_p]),
+            "gcge_orth_mbo": (c_int, [c_int64, c_int, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int64, c_int,
+                                      c_int, c_void_p, c_void_p]),
             "gcge_small_eigh": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_int]),
             "gcge_dense_eig": (c_int, [c_int, c_void_p, c_int64, c_int, c_void_p, c_void_p, c_int64, c_void_p]),
             "gcge_p_hat": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p]),

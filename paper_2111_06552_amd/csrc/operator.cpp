@@ -434,6 +434,107 @@ struct OrthCtx {
         return compact(s, k, keep, kept);
     }
 
+    // Algorithm 2 on columns [0, k): blocks of b consecutive columns; inside a
+    // block each column is B-orthogonalized against the block's kept columns
+    // by Gram-Schmidt (two passes, one reduction each: the coefficients and
+    // the column's own squared B-norm, the norm after the projection following
+    // by Pythagoras), normalized or dropped (squared B-norm ratio at most
+    // drop_tol), then the block's kept columns are deflated from all later
+    // columns (repeated until the coefficients are small).  Kept columns are
+    // moved to the front as they are accepted.
+    int mbo(int k, int b, int *kept) {
+        int out = 0, cur = 0;
+        hipError_t e = ws.ensure_colvec(sizeof(double) * 16);
+        if (e != hipSuccess) return fail(e, "workspace");
+        while (cur < k) {
+            const int blk_end = std::min(cur + b, k);
+            const int bs0 = out;
+            for (int j = cur; j < blk_end; ++j) {
+                // one reduction per pass: [U, w]^T B w gives the coefficients
+                // against the block's kept columns U and the squared B-norm of w
+                double nrm0 = 0.0, nrm = 0.0;
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int nu = out - bs0;
+                    Segs X;
+                    std::vector<double> c;
+                    int rc;
+                    if (csr()) {
+                        X.add(BW + bs0, ldbw, nu);
+                        X.add(BW + j, ldbw, 1);
+                    } else {
+                        X.add(W + bs0, ldw, nu);
+                        X.add(W + j, ldw, 1);
+                    }
+                    rc = gram_host(X, W + j, ldw, 1, csr(), c);
+                    if (rc) return rc;
+                    double cc = 0.0;
+                    for (int i = 0; i < nu; ++i) cc += c[i] * c[i];
+                    if (pass == 0) nrm0 = c[nu];
+                    nrm = c[nu] - cc;   // squared B-norm after this pass's projection
+                    if (nu == 0) break;
+                    c.resize(nu);
+                    Segs Uw;
+                    Uw.add(W + bs0, ldw, nu);
+                    rc = gemm_host(Uw, c, 1, -1.0, 1.0, W + j, ldw);
+                    if (rc) return rc;
+                    if (csr()) {
+                        Segs Ub;
+                        Ub.add(BW + bs0, ldbw, nu);
+                        rc = gemm_host(Ub, c, 1, -1.0, 1.0, BW + j, ldbw);
+                        if (rc) return rc;
+                    }
+                }
+                // columns enter with unit B-norm (normalized after the deflation
+                // against Q), so the squared norm left is compared with drop_tol
+                // itself: a column that the deflations of earlier blocks reduced
+                // to rounding is dependent too
+                const bool keep = nrm0 > 0.0 && std::isfinite(nrm) && nrm > opt.drop_tol;
+                if (!keep) {
+                    if (os) os->dropped++;
+                    continue;
+                }
+                const double sc = 1.0 / std::sqrt(nrm);
+                e = stg.upload(ws.colvec, &sc, sizeof(double));
+                if (e == hipSuccess) e = copy_cols<double, double>(n, 1, W + j, ldw, W + out, ldw, ws.colvec, st);
+                if (e == hipSuccess && csr()) e = copy_cols<double, double>(n, 1, BW + j, ldbw, BW + out, ldbw, ws.colvec, st);
+                if (e != hipSuccess) return fail(e, "normalize");
+                ++out;
+            }
+            const int nb = out - bs0, nr = k - blk_end;
+            if (nb > 0 && nr > 0) {
+                for (int pass = 0; pass < opt.max_pass; ++pass) {
+                    Segs X1;
+                    std::vector<double> R;
+                    int rc;
+                    if (csr()) {
+                        X1.add(BW + bs0, ldbw, nb);
+                        rc = gram_host(X1, W + blk_end, ldw, nr, true, R);
+                    } else {
+                        X1.add(W + bs0, ldw, nb);
+                        rc = gram_host(X1, W + blk_end, ldw, nr, false, R);
+                    }
+                    if (rc) return rc;
+                    double rmax = 0.0;
+                    for (double v : R) rmax = std::max(rmax, std::fabs(v));
+                    Segs W1;
+                    W1.add(W + bs0, ldw, nb);
+                    rc = gemm_host(W1, R, nr, -1.0, 1.0, W + blk_end, ldw);
+                    if (rc) return rc;
+                    if (csr()) {
+                        Segs B1;
+                        B1.add(BW + bs0, ldbw, nb);
+                        rc = gemm_host(B1, R, nr, -1.0, 1.0, BW + blk_end, ldbw);
+                        if (rc) return rc;
+                    }
+                    if (rmax <= opt.orth_tol) break;
+                }
+            }
+            cur = blk_end;
+        }
+        *kept = out;
+        return GCGE_OK;
+    }
+
     // Algorithm 3 on columns [s, e); returns kept count via *kept
     int rec(int s, int e, int *kept) {
         const int len = e - s;
@@ -566,9 +667,14 @@ int orth_block(int64_t n, const BOp &B, const Segs &Q, double *W, int64_t ldw, i
         }
     }
     if (kk == 0) return GCGE_OK;
-    C.c = std::min(kk, 16);
     int out = 0;
-    rc = C.rec(0, kk, &out);
+    if (opt.algorithm == 2) {
+        const int b = opt.mbo_block > 0 ? opt.mbo_block : std::max(1, std::min(kk / 4, 200));
+        rc = C.mbo(kk, b, &out);
+    } else {
+        C.c = std::min(kk, 16);
+        rc = C.rec(0, kk, &out);
+    }
     if (rc) return rc;
     *kept = out;
     return GCGE_OK;

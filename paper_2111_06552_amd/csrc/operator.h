@@ -85,10 +85,12 @@ struct OrthOptions {
     double orth_tol = 1e-13;
     double drop_tol = 1e-8;
     int max_pass = 3;
+    int algorithm = 3;   // 3: RecursiveOrthSVD (Algorithm 3); 2: modified block orthogonalization (Algorithm 2)
+    int mbo_block = 0;   // block size b of Algorithm 2 (0: min(m/4, 200))
 };
 
 // B-orthonormalize the n x k block W (ld) against the B-orthonormal block Q
-// and within itself (Algorithm 3).  BW: n x k scratch (used for CSR B).  On
+// and within itself (Algorithm 3, or Algorithm 2 when opt.algorithm == 2).  BW: n x k scratch (used for CSR B).  On
 // success *kept holds the number of output columns (W compacted).
 int orth_block(int64_t n, const BOp &B, const Segs &Q, double *W, int64_t ldw, int k, double *BW, int64_t ldbw,
                const OrthOptions &opt, Workspace &ws, Stager &stg, hipStream_t st, int *kept, OrthStats *os,

@@ -214,6 +214,7 @@ struct gcge_handle_s {
     int profile = 0;
     KProf prof;
     int dense_eig_opt = 1;
+    int orth_alg = 3, orth_block_opt = 0;
     DenseEigWork eigw;
     double *rrbuf = nullptr;   // device: Abar, its eigenvalues and eigenvectors
     size_t rrcap = 0;
@@ -463,6 +464,8 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     OrthOptions oo;
     oo.orth_tol = orth_tol;
     oo.drop_tol = drop_tol;
+    oo.algorithm = orth_alg;
+    oo.mbo_block = orth_block_opt;
     OrthStats ostat;
 
     // ---------------- STEPs 1-3, first pass: random block, orthogonalize, Rayleigh-Ritz
@@ -797,6 +800,8 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "check") { if (v != 0 && v != 1) return bad(); h->check = (int)v; }
     else if (k == "profile") { if (v != 0 && v != 1) return bad(); h->profile = (int)v; }
     else if (k == "dense_eig") { if (v != 0 && v != 1) return bad(); h->dense_eig_opt = (int)v; }
+    else if (k == "orth") { if (v != 2 && v != 3) return bad(); h->orth_alg = (int)v; }
+    else if (k == "orth_block") { if (v < 0 || v > 100000) return bad(); h->orth_block_opt = (int)v; }
     else return h->fail(GCGE_ERR_INVALID_ARG, "unknown option " + k);
     return GCGE_OK;
 }
@@ -1170,8 +1175,8 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
     }
 }
 
-extern "C" int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq, double *W,
-                         int64_t ldw, int k, int *kept, void *stream) {
+static int orth_entry(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq, double *W,
+                      int64_t ldw, int k, int *kept, void *stream, const OrthOptions &oo) {
     if (n < 1 || k < 0 || mq < 0 || !kept || (k > 0 && (!W || ldw < k)) || (mq > 0 && (!Q || ldq < mq)) ||
         (b_kind != GCGE_B_IDENTITY && b_kind != GCGE_B_DIAG && b_kind != GCGE_B_CSR) ||
         (b_kind != GCGE_B_IDENTITY && !B) || (b_kind == GCGE_B_CSR && !csr_ok((const gcge_csr *)B)))
@@ -1195,7 +1200,6 @@ extern "C" int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, 
         if (e != hipSuccess) return step_hip(e, "gcge_orth");
         Segs QS;
         QS.add(Q, ldq, mq);
-        OrthOptions oo;
         std::string err;
         int rc = orth_block(n, bop, QS, W, ldw, k, BW, ldbw, oo, C.ws, C.stg, st, kept, nullptr, err);
         if (!rc) e = C.stg.sync();
@@ -1206,6 +1210,21 @@ extern "C" int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, 
     } catch (...) {
         return step_fail(GCGE_ERR_INTERNAL, "gcge_orth: internal error");
     }
+}
+
+extern "C" int gcge_orth(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq, double *W,
+                         int64_t ldw, int k, int *kept, void *stream) {
+    OrthOptions oo;
+    return orth_entry(n, b_kind, B, Q, ldq, mq, W, ldw, k, kept, stream, oo);
+}
+
+extern "C" int gcge_orth_mbo(int64_t n, int b_kind, const void *B, const double *Q, int64_t ldq, int mq, double *W,
+                             int64_t ldw, int k, int block, int *kept, void *stream) {
+    if (block < 0) return step_fail(GCGE_ERR_INVALID_ARG, "gcge_orth_mbo: invalid argument");
+    OrthOptions oo;
+    oo.algorithm = 2;
+    oo.mbo_block = block;
+    return orth_entry(n, b_kind, B, Q, ldq, mq, W, ldw, k, kept, stream, oo);
 }
 
 extern "C" int gcge_small_eigh(int n, double *a, double *w, double *z, int nwant) {

@@ -243,6 +243,42 @@ def test_orth_invariants_and_kept_count(g, bkind):
     assert np.max(np.abs(proj - W0)) < 1e-11 * np.max(np.abs(W0))
 
 
+@pytest.mark.parametrize("bkind", ["identity", "diag", "csr"])
+@pytest.mark.parametrize("block", [0, 5])
+def test_orth_algorithm2_invariants_and_kept_count(g, bkind, block):
+    """Modified block orthogonalization (Algorithm 2) against the oracle's: the
+    same deflation against Q, then blocks of b columns (default min(m/4, 200))."""
+    A, Bq = wl.q1_fem(9)
+    n = A.n
+    if bkind == "identity":
+        Bd, ok, ob = None, "identity", None
+    elif bkind == "diag":
+        d = wl.diag_uniform(n)
+        Bd, ok, ob = dev(d), "diag", d
+    else:
+        Bd, ok, ob = g.DeviceCsr.from_csr(Bq), "csr", Bq
+    Q0 = RNG.standard_normal((n, 30))
+    Q, kq = orc.recursive_orth_svd(Q0, ok, ob)
+    W0 = RNG.standard_normal((n, 41))
+    W0[:, 7] = W0[:, 3]                        # duplicate inside a block
+    W0[:, 20] = Q[:, 5] * 2.0                  # inside span(Q)
+    W0[:, 33] = W0[:, 1] - 0.5 * W0[:, 30]     # dependent across blocks
+    Wo = host(g.orth(dev(W0), dev(Q), Bd, algorithm=2, block=block))
+    kept = Wo.shape[1]
+    ref, _ = orc.deflate(W0, Q, ok, ob)
+    b = block if block > 0 else max(1, min(ref.shape[1] // 4, 200))
+    ref, kref = orc.modified_block_orth(ref, None, ok, ob, b=b, drop_tol=1e-4)
+    assert kept == kref == 38
+    BW = orc.apply_b(ok, ob, Wo)
+    assert np.max(np.abs(Wo.T @ BW - np.eye(kept))) < 1e-13
+    assert np.max(np.abs(Q.T @ BW)) < 1e-13
+    # the kept columns are those of the oracle up to rounding (Gram-Schmidt fixes them)
+    assert np.max(np.abs(Wo - ref)) < 1e-9
+    V = np.hstack([Q, Wo])
+    proj = V @ (V.T @ orc.apply_b(ok, ob, W0))
+    assert np.max(np.abs(proj - W0)) < 1e-11 * np.max(np.abs(W0))
+
+
 def test_pattern_grad_matches_formula(g):
     A = wl.varcoef3d_7pt(8)
     X = RNG.standard_normal((A.n, 37))

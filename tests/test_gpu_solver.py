@@ -97,6 +97,22 @@ def test_reduced_grid_parity_with_oracle(g, name, make, nev, opts):
         assert st["moves"] >= 1
 
 
+@pytest.mark.parametrize("name,make,nev,opts", [
+    ("lap3d_10_diagB_alg2", lambda: (wl.laplace3d_7pt(10), "diag", wl.diag_uniform(1000)), 20,
+     dict(block_size=5, orth=2)),
+    ("q1fem_9_moving_alg2", lambda: (wl.q1_fem(9)[0], "csr", wl.q1_fem(9)[1]), 60,
+     dict(block_size=10, moving=1, orth=2, orth_block=4)),
+])
+def test_reduced_grid_parity_algorithm2(g, name, make, nev, opts):
+    """The solver with the modified block orthogonalization (Algorithm 2) in STEP 2."""
+    A, bkind, B = make()
+    lam, X, st = gpu_solve(g, A, bkind, B, nev, **opts)
+    lam_o, X_o = orc.pencil_eigs(A, bkind, B, nev + 6)
+    assert np.max(np.abs(lam - lam_o[:nev]) / np.abs(lam_o[:nev])) < 1e-10
+    check_pairs(A, bkind, B, lam, X, 1e-8)
+    compare_vectors(bkind, B, lam_o, X_o, X, nev)
+
+
 def test_deterministic(g):
     A = wl.laplace3d_7pt(12)
     d = wl.diag_uniform(A.n)
