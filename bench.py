@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--workload", default="lap3d_7pt_128_diagB")
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--orth", type=int, choices=(2, 3), default=3,
+                    help="STEP 2 orthogonalization: 3 RecursiveOrthSVD (default), 2 modified block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown table of a rocprofv3 --stats run")
@@ -263,7 +265,7 @@ def main():
     evecs = torch.empty((A.n, nev), dtype=torch.float64, device=dev)
 
     def run(prec, steps, warmup):
-        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1)
+        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1, orth=args.orth)
         with g.Solver(Ad, Bd, nev, tol, **opts) as s:
             for i in range(warmup):
                 lam, _, st = s.solve(evecs)
@@ -287,7 +289,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": float(t64.mean() * 1e3), "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "grid": p["grid"], "n": A.n, "nnz": A.nnz, "nev": nev,
-                   "block_size": bs, "tol": tol, "B": bkind, "moving": bool(p["moving"])},
+                   "block_size": bs, "tol": tol, "B": bkind, "moving": bool(p["moving"]),
+                   "orthogonalization": "Algorithm 3" if args.orth == 3 else "Algorithm 2"},
     }
     st = s64[-1]
     out["solve"] = {k: st[k] for k in ("iterations", "nconv", "moves", "cg_iterations", "spmm_columns",
