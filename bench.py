@@ -219,6 +219,11 @@ def main():
     ap.add_argument("--workload", default="lap3d_7pt_128_diagB")
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cg-max-iter", type=int, default=30, help="inner CG iterations per GCG iteration (cap)")
+    ap.add_argument("--cg-rel-tol", type=float, default=1e-2,
+                    help="inner CG stop at this relative residual (0: always cg-max-iter iterations)")
+    ap.add_argument("--shift", type=int, choices=(0, 1), default=1,
+                    help="1: inner CG on A - theta B with theta the largest converged eigenvalue; 0: theta = 0")
     ap.add_argument("--orth", type=int, choices=(2, 3), default=3,
                     help="STEP 2 orthogonalization: 3 RecursiveOrthSVD (default), 2 modified block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -265,7 +270,8 @@ def main():
     evecs = torch.empty((A.n, nev), dtype=torch.float64, device=dev)
 
     def run(prec, steps, warmup):
-        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1, orth=args.orth)
+        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1, orth=args.orth,
+                    cg_max_iter=args.cg_max_iter, cg_rel_tol=args.cg_rel_tol, shift=args.shift)
         with g.Solver(Ad, Bd, nev, tol, **opts) as s:
             for i in range(warmup):
                 lam, _, st = s.solve(evecs)
@@ -290,7 +296,8 @@ def main():
         "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "grid": p["grid"], "n": A.n, "nnz": A.nnz, "nev": nev,
                    "block_size": bs, "tol": tol, "B": bkind, "moving": bool(p["moving"]),
-                   "orthogonalization": "Algorithm 3" if args.orth == 3 else "Algorithm 2"},
+                   "orthogonalization": "Algorithm 3" if args.orth == 3 else "Algorithm 2",
+                   "cg_max_iter": args.cg_max_iter, "cg_rel_tol": args.cg_rel_tol, "shift": bool(args.shift)},
     }
     st = s64[-1]
     out["solve"] = {k: st[k] for k in ("iterations", "nconv", "moves", "cg_iterations", "spmm_columns",

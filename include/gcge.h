@@ -135,7 +135,8 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
 
-/* Double options: "tol", "cg_rel_tol" [1e-2] (Section 4.1), "orth_tol" [1e-13]
+/* Double options: "tol", "cg_rel_tol" [1e-2] (Section 4.1; 0 runs cg_max_iter
+ * iterations on every column), "orth_tol" [1e-13]
  * (the "small enough" tests of Algorithm 3), "drop_tol" [1e-8] (eigenvalue of a
  * leaf Gram of unit-B-norm columns at or below which a direction counts as
  * linearly dependent and is dropped). */

@@ -809,7 +809,9 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
 extern "C" int gcge_set_option_d(gcge_handle h, const char *key, double v) {
     if (!h || !key) return GCGE_ERR_INVALID_ARG;
     const std::string k(key);
-    if (!(v > 0.0) || !std::isfinite(v)) return h->fail(GCGE_ERR_INVALID_ARG, "bad value for option " + k);
+    const bool zero_ok = (k == "cg_rel_tol");   // 0: every column takes cg_max_iter iterations
+    if (!std::isfinite(v) || v < 0.0 || (v == 0.0 && !zero_ok))
+        return h->fail(GCGE_ERR_INVALID_ARG, "bad value for option " + k);
     if (k == "tol") h->tol = v;
     else if (k == "cg_rel_tol") h->cg_rel_tol = v;
     else if (k == "orth_tol") h->orth_tol = v;
