@@ -228,6 +228,13 @@ template <typename T, int V>
 __device__ __forceinline__ void vst(T *p, const Vec<T, V> &x) {
     *reinterpret_cast<Vec<T, V> *>(p) = x;
 }
+// streaming store (not kept in L2): the SpMM's output rows, so that L2 keeps
+// the gathered input rows instead of dirty output lines
+template <typename T, int V>
+__device__ __forceinline__ void vst_nt(T *p, const Vec<T, V> &x) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) __builtin_nontemporal_store(x.v[v], p + v);
+}
 
 // SpMM with 16-byte vector accesses: a group of G lanes per row, lane l owns
 // columns V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 8,
@@ -473,7 +480,7 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                     acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
                 }
             }
-            vst<T, V>(Y + row * ldy + c0, acc);
+            vst_nt<T, V>(Y + row * ldy + c0, acc);
             if (RED == 1) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
