@@ -237,3 +237,54 @@ def test_gradient_diag_B_reduced_grid(g):
             vals.append(float(np.dot(w, s.solve()[0].numpy())))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - float(host(gB)[j])) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_gradient_csr_B_reduced_grid(g):
+    """Gradients with respect to the stored nonzeros of A and of a CSR B (Q1
+    stiffness and consistent mass on a 7^3 grid with random cell coefficients):
+    the backward kernels against the gradient formula on the oracle's
+    eigenvectors, and the autograd path against central differences of
+    warm-started solves on entries of both matrices."""
+    A, Bm = wl.q1_fem(7)
+    nev = 6
+    w = wl.loss_weights(nev)
+    lam_o, X_o = orc.pencil_eigs(A, "csr", Bm, nev + 1)
+    assert np.min(np.diff(lam_o)) > 1e-6 * lam_o[-1]
+    refA = orc.eig_grad(A, X_o[:, :nev], lam_o[:nev], w)
+    refB = orc.eig_grad(Bm, X_o[:, :nev], lam_o[:nev], w, kind="B")
+    Ad = g.DeviceCsr.from_csr(A)
+    Bd = g.DeviceCsr.from_csr(Bm)
+    a_val = torch.as_tensor(A.val, dtype=torch.float64, device="cuda")
+    b_val = torch.as_tensor(Bm.val, dtype=torch.float64, device="cuda")
+    with g.Solver(Ad, Bd, nev, 1e-11, block_size=3) as s:
+        a = a_val.clone().requires_grad_(True)
+        b = b_val.clone().requires_grad_(True)
+        lam = g.eigvals(a, s, b)
+        (torch.as_tensor(w, device=lam.device) * lam).sum().backward()
+        gA, gB = host(a.grad), host(b.grad)
+        assert np.max(np.abs(lam.detach().cpu().numpy() - lam_o[:nev]) / lam_o[:nev]) < 1e-10
+        assert np.max(np.abs(gA - refA)) <= 1e-8 * np.max(np.abs(refA))
+        assert np.max(np.abs(gB - refB)) <= 1e-8 * np.max(np.abs(refB))
+        X = s.last_evecs.clone()
+        for M, vals, grad, which in ((A, a_val, gA, "A"), (Bm, b_val, gB, "B")):
+            for e in wl.fd_sample(M, count=4, seed=57):
+                r, c, t = transposed_entry(M, int(e))
+                # step relative to the matrix's largest entry (entries range over
+                # orders of magnitude, some are stored zeros)
+                h = 1e-6 * np.max(np.abs(M.val))
+                f = []
+                for sgn in (1.0, -1.0):
+                    v = vals.clone()
+                    v[e] += sgn * h
+                    if t != e:
+                        v[t] += sgn * h
+                    if which == "A":
+                        s.update_values(v, b_val)
+                    else:
+                        s.update_values(a_val, v)
+                    s.set_initial_vectors(X)
+                    f.append(float(np.dot(w, s.solve()[0].numpy())))
+                fd = (f[0] - f[1]) / (2 * h)
+                an = grad[e] + (grad[t] if t != e else 0.0)
+                assert abs(fd - an) <= 1e-5 * abs(an) + 1e-9, (which, int(e), fd, an)
+        s.update_values(a_val, b_val)
