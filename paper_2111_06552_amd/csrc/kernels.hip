@@ -1531,9 +1531,43 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmParams P) {
         }
 }
 
+// Narrow products (at most 32 input and 32 output columns, one X segment):
+// a group of G lanes per row, lane l holding input column l and output
+// column l; the input row is broadcast across the group by shuffles and S is
+// read from LDS.  Each row depends only on itself, so Y may alias X.
+template <int G>
+__global__ __launch_bounds__(256) void k_gemm_rows(int64_t n, const double *__restrict__ X, int64_t ldx, int m,
+                                                   const double *__restrict__ S, int64_t lds, int k, double alpha,
+                                                   double beta, double *Y, int64_t ldy) {
+    __shared__ double Ss[32 * 32];
+    for (int i = threadIdx.x; i < m * k; i += 256) Ss[i] = S[(int64_t)(i / k) * lds + i % k];
+    __syncthreads();
+    constexpr int NGR = 256 / G;
+    const int grp = threadIdx.x / G, l = threadIdx.x % G;
+    const int lx = l < m ? l : 0, ly = l < k ? l : 0;   // clamped columns: loads carry no branch
+    for (int64_t row = (int64_t)blockIdx.x * NGR + grp; row < n; row += (int64_t)gridDim.x * NGR) {
+        const double xv = X[row * ldx + lx];
+        const double yo = (beta != 0.0) ? Y[row * ldy + ly] : 0.0;
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc = fma(__shfl(xv, j, G), Ss[j * k + ly], acc);
+        if (l < k) Y[row * ldy + l] = (beta != 0.0) ? fma(beta, yo, alpha * acc) : alpha * acc;
+    }
+}
+
 hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
                 double *Y, int64_t ldy, hipStream_t st) {
     if (n == 0 || k == 0) return hipSuccess;
+    if (X.nseg == 1 && X.s[0].ncol <= 32 && k <= 32) {
+        const int m = X.s[0].ncol, w = std::max(m, k);
+        const int G = w <= 8 ? 8 : w <= 16 ? 16 : 32;
+        const int64_t nb = std::min<int64_t>((n + 256 / G - 1) / (256 / G), (int64_t)num_cu() * 16);
+#define GCGE_GR(Gv)                                                                                          \
+    if (G == Gv) hipLaunchKernelGGL(k_gemm_rows<Gv>, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, \
+                                    S, lds, k, alpha, beta, Y, ldy);
+        GCGE_GR(8) GCGE_GR(16) GCGE_GR(32)
+#undef GCGE_GR
+        return hipGetLastError();
+    }
     GemmParams P;
     P.n = n;
     P.nseg = X.nseg;

@@ -124,8 +124,8 @@ def test_gram(g, n, m, k):
     assert np.array_equal(C1, C2)   # fixed summation order
 
 
-@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (63, 5, 3), (1000, 16, 16), (4099, 50, 50), (5000, 450, 350),
-                                   (777, 100, 130)])
+@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (63, 5, 3), (1000, 16, 16), (5001, 25, 32), (2049, 32, 7),
+                                   (100, 3, 32), (4099, 50, 50), (5000, 450, 350), (777, 100, 130)])
 def test_gemm_update(g, n, m, k):
     X = RNG.standard_normal((n, m))
     S = RNG.standard_normal((m, k))
@@ -136,14 +136,19 @@ def test_gemm_update(g, n, m, k):
     assert np.all(np.abs(host(Y) - ref) <= 1e-13 * bound)
 
 
-def test_gemm_in_place_row_transform(g):
-    n, k = 3001, 16
-    X = RNG.standard_normal((n, k))
-    S = RNG.standard_normal((k, 12))
-    Xd = dev(X)
-    g.gemm_update(Xd, S, Xd[:, :12])
-    out = host(Xd)[:, :12]
-    assert np.max(np.abs(out - X @ S)) <= 1e-13 * np.max(np.abs(X) @ np.abs(S))
+@pytest.mark.parametrize("s0,k,kout", [(0, 16, 12), (3, 25, 25), (7, 9, 16), (1, 60, 50)])
+def test_gemm_in_place_row_transform(g, s0, k, kout):
+    """Y aliases X (the in-place updates of Algorithm 3), columns starting at
+    an odd offset of a wider block."""
+    n = 3001
+    W = RNG.standard_normal((n, 64))
+    S = RNG.standard_normal((k, kout))
+    Wd = dev(W)
+    X = W[:, s0:s0 + k].copy()
+    g.gemm_update(Wd[:, s0:s0 + k], S, Wd[:, s0:s0 + kout])
+    out = host(Wd)
+    assert np.max(np.abs(out[:, s0:s0 + kout] - X @ S)) <= 1e-13 * np.max(np.abs(X) @ np.abs(S))
+    assert np.array_equal(out[:, :s0], W[:, :s0]) and np.array_equal(out[:, s0 + kout:], W[:, s0 + kout:])
 
 
 @pytest.mark.parametrize("maxit", [1, 2, 5, 30])
