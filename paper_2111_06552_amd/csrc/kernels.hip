@@ -1591,7 +1591,7 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
     const int64_t nrt = (n + 127) / 128;
     const int64_t nb = nrt * P.nct;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    if (BN == 64) hipLaunchKernelGGL((k_gemm<128, 64, 32, 2, 2>), dim3((unsigned)nb), dim3(256), 0, st, P);
+    if (BN == 64) hipLaunchKernelGGL((k_gemm<128, 64, 32, 4, 2>), dim3((unsigned)nb), dim3(512), 0, st, P);
     else hipLaunchKernelGGL((k_gemm<128, 128, 16, 4, 2>), dim3((unsigned)nb), dim3(512), 0, st, P);
     return hipGetLastError();
 }
