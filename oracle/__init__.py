@@ -15,7 +15,9 @@ parallel block damping inverse power method") that it follows.
 
 Parity status of each function is listed in :data:`PINS`; every function is
 pinned by at least one check that does not reuse its own formula (closed
-forms, brute force, invariants) in ``tests/test_oracle_pins.py``.
+forms, brute force, invariants) in ``tests/test_oracle_pins.py`` and
+``tests/test_oracle_amg_pins.py``.
 """
 from .core import *  # noqa: F401,F403
 from .core import PINS  # noqa: F401
+from . import amg  # noqa: F401

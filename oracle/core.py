@@ -44,6 +44,13 @@ PINS = {
     "p_hat": "[xhat, phat]^T [xhat, phat] = I; zero rows; rank loss on a complete xhat",
     "eig_grad": "central finite differences of pencil_eigs on small random pencils",
     "moving_memory": "parity unpinned beyond direct evaluation of the paper's formula (weak pin)",
+    "amg.aggregate": "hand-derived aggregates of the 1D Laplacian and of small graphs (strongest-link "
+                     "rule, tie margin, weak links); partition of the rows",
+    "amg.amg_setup": "hand-derived smoothed prolongator column (1D); P_t^T P_t = I; the V-cycle checks below",
+    "amg.amg_vcycle": "one level equals numpy.linalg.solve; symmetric positive definite; error "
+                      "propagation I - V A contracts (spectral radius < 0.7) on 2D/3D stencils",
+    "amg.pcg_columnwise": "exact preconditioner converges in one step to numpy.linalg.solve; solves "
+                          "A x = r to 1e-10; far fewer iterations than plain CG",
 }
 
 
