@@ -132,6 +132,14 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "dense_eig"    [1]     small Rayleigh-Ritz eigenproblem on the device (gcge_dense_eig)
  *                         when its order is at most 768; 0 solves it on the host
  *                         (gcge_small_eigh)
+ *  "precond"      [0]     1: STEP 6 runs preconditioned CG with the algebraic multigrid
+ *                         V-cycle of A (gcge_amg_create) and theta = 0, as Section 2
+ *                         suggests for discretized PDE operators; needs precision FP64
+ *                         (INVALID_ARG at gcge_solve otherwise).  The hierarchy is built
+ *                         at the first STEP 6 (its time counts in time_ms[5]) and again
+ *                         after gcge_update_values.
+ *  "amg_levels"   [10]    level limit of that hierarchy (1 .. 16)
+ *  "amg_coarse"   [512]   rows at or below which a level is the coarsest (1 .. 4096)
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
 
@@ -277,6 +285,61 @@ int gcge_dense_eig(int n, const double *a, int64_t lda, int nwant, double *w, do
  * phat: host dim x n_new row-major (first *np columns valid). */
 int gcge_p_hat(int dim, int nx, const double *xhat, int shift, int n_old, int n_new,
                double drop_tol, double *phat, int *np);
+
+/* ------------------------------------------------- STEP 6 preconditioner */
+
+/* Algebraic multigrid preconditioner of the STEP 6 systems.  Section 2
+ * suggests algebraic multigrid as the preconditioner of STEP 6 with theta = 0
+ * when A discretizes a PDE; the paper does not fix the method, so this is
+ * smoothed aggregation (Vanek, Mandel, Brezina 1996):
+ *   strength   |a_ij| >= eps_l sqrt(a_ii a_jj), eps_l = 0.08 * 2^-l at level l;
+ *   aggregates rows in order: a row whose strong neighbours are all free
+ *              seeds an aggregate with them; a row left joins the aggregate
+ *              of its strongest already aggregated neighbour (first in column
+ *              order among those within a relative 1e-8 of the largest);
+ *   transfer   P = (I - omega D^-1 A) P_t with P_t the normalized aggregate
+ *              indicators, omega = 4/(3 rho), rho = max_i sum_j |a_ij| / a_ii;
+ *              R = P^T, next level R A P;
+ *   coarsest   at most coarse_max rows, the level limit, or no coarsening:
+ *              inverted densely (at most 4096 rows, INVALID_ARG otherwise);
+ *   V-cycle    one damped Jacobi sweep (omega D^-1) before and after the
+ *              coarse correction, from a zero guess: symmetric positive
+ *              definite for SPD A.
+ */
+typedef struct gcge_amg_s *gcge_amg;
+
+/* Build the hierarchy of the SPD matrix A (device CSR, borrowed: the level-0
+ * operator is read from it at every gcge_amg_apply / gcge_pcg, so it must
+ * stay alive and unchanged until gcge_amg_destroy).  The setup runs on the
+ * host (A is copied down once); the coarse levels live in device memory owned
+ * by the handle.  max_levels in 1 .. 16, coarse_max in 1 .. 4096.  Errors:
+ * INVALID_ARG, NOT_SPD (a non-positive diagonal entry, or a coarsest level
+ * that is not positive definite), OOM, HIP. */
+int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, void *stream, gcge_amg *out);
+
+/* Number of levels (the last one is the dense coarsest level) and, for the
+ * first min(levels, cap), the rows and stored entries of each level operator
+ * (host arrays). */
+int gcge_amg_levels(gcge_amg h, int *nlevels, int64_t *rows, int64_t *nnz, int cap);
+
+/* Aggregate index of every row of level `level` (0 .. levels - 2) into the
+ * host array agg[rows(level)]. */
+int gcge_amg_aggregates(gcge_amg h, int level, int32_t *agg);
+
+/* Y = V(B): one V-cycle applied to the k <= 128 columns of B (device, n x k
+ * row-major, ldb) into Y (device, ldy).  Calls on one handle are serialized
+ * (the work vectors belong to the handle).  Asynchronous on stream. */
+int gcge_amg_apply(gcge_amg h, const double *B, int64_t ldb, int k, double *Y, int64_t ldy, void *stream);
+
+/* STEP 6 with preconditioning: column-wise preconditioned CG on A delta = R
+ * (theta = 0) from delta = 0 with M^-1 = the V-cycle of h (built from A);
+ * a column stops when ||r|| <= rel_tol ||r_0||, after maxit iterations, or
+ * when p^T A p <= 0.  Arguments as gcge_cg (FP64 only). */
+int gcge_pcg(const gcge_csr *A, gcge_amg h, const double *R, int64_t ldr, int k, int maxit, double rel_tol,
+             double *delta, int64_t ldd, int *its, void *stream);
+
+/* Release the hierarchy (synchronizes the device first). */
+void gcge_amg_destroy(gcge_amg h);
 
 /* Eigenvalue-gradient kernel: gval[e] = sum_i wts[i] X[r_e, i] X[c_e, i] over
  * the stored entries e = (r_e, c_e) of the pattern (rowptr, colind) (device),

@@ -22,7 +22,7 @@ from ._lib import (B_CSR, B_DIAG, B_IDENTITY, GCGE_NOT_CONVERGED, GCGE_OK, PREC_
 
 __all__ = [
     "DeviceCsr", "Solver", "solve", "GcgeEig", "eigvals", "spmm", "spmm_f32", "shifted_spmm", "residual", "gram",
-    "gemm_update", "cg", "orth", "small_eigh", "p_hat", "pattern_grad", "GcgeError", "library_path",
+    "gemm_update", "cg", "orth", "small_eigh", "p_hat", "pattern_grad", "GcgeError", "library_path", "Amg", "pcg",
 ]
 
 
@@ -95,7 +95,7 @@ def _b_args(B):
 
 
 _INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
-             "dense_eig", "orth", "orth_block",
+             "dense_eig", "orth", "orth_block", "precond", "amg_levels", "amg_coarse",
              "profile"}
 _DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol"}
 
@@ -338,6 +338,77 @@ def cg(A: DeviceCsr, B, theta: float, R: torch.Tensor, maxit: int = 30, rel_tol:
     prec = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
     _lib.check(_L().gcge_cg(ctypes.byref(c), kind, bp, float(theta), pr, ldr, k, int(maxit), float(rel_tol), prec,
                             pd, ldd, its.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(_stream(R.device))))
+    return D, its
+
+
+class Amg:
+    """Algebraic multigrid preconditioner of the STEP 6 systems (gcge_amg_*).
+
+    Keeps a reference to A: its device arrays are the level-0 operator."""
+
+    def __init__(self, A: DeviceCsr, max_levels: int = 10, coarse_max: int = 512):
+        self._A = A
+        self._c = A.c()
+        h = ctypes.c_void_p()
+        _lib.check(_L().gcge_amg_create(ctypes.byref(self._c), int(max_levels), int(coarse_max),
+                                        ctypes.c_void_p(_stream(A.rowptr.device)), ctypes.byref(h)))
+        self._h = h
+
+    def levels(self):
+        """[(rows, stored entries)] per level; the last level is the dense coarsest one."""
+        cap = 16
+        rows = np.zeros(cap, dtype=np.int64)
+        nnz = np.zeros(cap, dtype=np.int64)
+        nl = ctypes.c_int(0)
+        _lib.check(_L().gcge_amg_levels(self._h, ctypes.byref(nl), rows.ctypes.data_as(ctypes.c_void_p),
+                                        nnz.ctypes.data_as(ctypes.c_void_p), cap))
+        return [(int(rows[i]), int(nnz[i])) for i in range(nl.value)]
+
+    def aggregates(self, level: int) -> np.ndarray:
+        rows = self.levels()[level][0]
+        agg = np.zeros(rows, dtype=np.int32)
+        _lib.check(_L().gcge_amg_aggregates(self._h, int(level), agg.ctypes.data_as(ctypes.c_void_p)))
+        return agg
+
+    def apply(self, Bm: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
+        """Y = V(B), one V-cycle on the columns of B (n x k, k <= 128)."""
+        _check_dev(Bm, torch.float64, "B")
+        if Y is None:
+            Y = torch.empty_like(Bm)
+        pb, ldb = _rowmajor(Bm, "B")
+        py, ldy = _rowmajor(Y, "Y")
+        _lib.check(_L().gcge_amg_apply(self._h, pb, ldb, Bm.shape[1], py, ldy, ctypes.c_void_p(_stream(Bm.device))))
+        return Y
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _L().gcge_amg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def pcg(A: DeviceCsr, M: Amg, R: torch.Tensor, maxit: int = 30, rel_tol: float = 1e-2):
+    """STEP 6 preconditioned by the V-cycle of M (theta = 0): (delta, iterations per column)."""
+    _check_dev(R, torch.float64, "R")
+    k = R.shape[1]
+    D = torch.empty_like(R)
+    its = np.zeros(k, dtype=np.int32)
+    pr, ldr = _rowmajor(R, "R")
+    pd, ldd = _rowmajor(D, "delta")
+    c = A.c()
+    _lib.check(_L().gcge_pcg(ctypes.byref(c), M._h, pr, ldr, k, int(maxit), float(rel_tol), pd, ldd,
+                             its.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(_stream(R.device))))
     return D, its
 
 

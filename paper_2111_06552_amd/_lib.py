@@ -18,7 +18,7 @@ GCGE_ERR_INTERNAL = -5
 B_IDENTITY, B_DIAG, B_CSR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
-PROF_NAMES = ["cg_spmm", "cg_update_r", "cg_update_xp", "rotation_gemm", "p_gemm", "gram", "unused6", "unused7"]
+PROF_NAMES = ["cg_spmm", "cg_update_r", "cg_update_xp", "rotation_gemm", "p_gemm", "gram", "amg_vcycle", "unused7"]
 STEP_NAMES = ["init", "step2_orth", "step3_rr", "step4_conv", "step5_p", "step6_cg", "final_check", "total"]
 
 # Every symbol declared in include/gcge.h.
@@ -27,6 +27,7 @@ EXPORTED = [
     "gcge_solve", "gcge_update_values", "gcge_eig_grad", "gcge_destroy", "gcge_last_error", "gcge_spmm",
     "gcge_spmm_f32", "gcge_shifted_spmm", "gcge_residual", "gcge_gram", "gcge_gemm_update", "gcge_cg",
     "gcge_orth", "gcge_orth_mbo", "gcge_small_eigh", "gcge_dense_eig", "gcge_p_hat", "gcge_pattern_grad",
+    "gcge_amg_create", "gcge_amg_levels", "gcge_amg_aggregates", "gcge_amg_apply", "gcge_pcg", "gcge_amg_destroy",
 ]
 
 
@@ -113,6 +114,13 @@ def load():
             "gcge_p_hat": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p]),
             "gcge_pattern_grad": (c_int, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_void_p,
                                           c_void_p, c_void_p]),
+            "gcge_amg_create": (c_int, [P(Csr), c_int, c_int, c_void_p, P(c_void_p)]),
+            "gcge_amg_levels": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p, c_int]),
+            "gcge_amg_aggregates": (c_int, [c_void_p, c_int, c_void_p]),
+            "gcge_amg_apply": (c_int, [c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int64, c_void_p]),
+            "gcge_pcg": (c_int, [P(Csr), c_void_p, c_void_p, c_int64, c_int, c_int, c_double, c_void_p, c_int64,
+                                 c_void_p, c_void_p]),
+            "gcge_amg_destroy": (None, [c_void_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)

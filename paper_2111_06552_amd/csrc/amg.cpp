@@ -1,0 +1,515 @@
+// Smoothed-aggregation algebraic multigrid, the preconditioner of the STEP 6
+// linear systems (Section 2 suggests an algebraic multigrid preconditioner for
+// STEP 6 with the shift theta = 0 when A comes from a PDE discretization).
+// The paper does not fix the AMG; this one is smoothed aggregation (Vanek,
+// Mandel and Brezina, Computing 56, 1996) with these choices:
+//   strength      j != i is strong for row i when |a_ij| >= eps_l sqrt(|a_ii a_jj|),
+//                 eps_l = 0.08 * 2^-l at level l;
+//   aggregation   rows in order; phase 1: a row whose strong neighbours are all
+//                 free seeds an aggregate with them (no strong neighbour: a
+//                 singleton); phase 2: a row left joins the phase-1 aggregate
+//                 of its strongest phase-1-aggregated neighbour (neighbours in
+//                 column order, a later one wins only when |a_ij| is larger
+//                 by a relative 1e-8, so rounding cannot change the choice);
+//   prolongator   P = (I - omega D^-1 A) P_t, P_t[i, agg(i)] = |agg(i)|^-1/2,
+//                 omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / a_ii;
+//   coarse level  R = P^T, A_next = R A P; the last level (at most coarse_max
+//                 rows, or the level limit, or no coarsening) is inverted
+//                 densely (Cholesky) and applied as a GEMM;
+//   V-cycle       x = w b (one damped Jacobi sweep from zero, w = omega D^-1),
+//                 t = b - A x, x += P V(R t), y = x + w (b - A x): symmetric
+//                 and positive definite, so it preconditions CG.
+// The setup runs on the host (OpenMP over rows; fixed summation orders, so
+// the hierarchy does not depend on the thread count); every step of the
+// V-cycle is a device kernel.
+#include "gcge.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace gcge {
+
+namespace {
+
+constexpr double STRENGTH_EPS0 = 0.08;
+constexpr double TIE_REL = 1e-8;
+
+int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP; }
+
+// host CSR, n rows x m columns, sorted unique column indices per row
+struct HCsr {
+    int64_t n = 0, m = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> va;
+    int64_t nnz() const { return rp.empty() ? 0 : rp[n]; }
+};
+
+bool diag_of(const HCsr &A, std::vector<double> &d) {
+    d.assign(A.n, 0.0);
+    for (int64_t i = 0; i < A.n; ++i)
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e)
+            if (A.ci[e] == i) d[i] = A.va[e];
+    for (int64_t i = 0; i < A.n; ++i)
+        if (!(d[i] > 0.0)) return false;
+    return true;
+}
+
+void aggregate(const HCsr &A, const std::vector<double> &d, double eps, std::vector<int32_t> &agg, int64_t &nagg) {
+    const int64_t n = A.n;
+    std::vector<uint8_t> strong(A.nnz());
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+            const int64_t j = A.ci[e];
+            strong[e] = (j != i && std::fabs(A.va[e]) >= eps * std::sqrt(std::fabs(d[i] * d[j]))) ? 1 : 0;
+        }
+    agg.assign(n, -1);
+    nagg = 0;
+    for (int64_t i = 0; i < n; ++i) {   // phase 1
+        if (agg[i] >= 0) continue;
+        bool free_nb = true;
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1] && free_nb; ++e)
+            if (strong[e] && agg[A.ci[e]] >= 0) free_nb = false;
+        if (!free_nb) continue;
+        agg[i] = (int32_t)nagg;
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e)
+            if (strong[e]) agg[A.ci[e]] = (int32_t)nagg;
+        ++nagg;
+    }
+    const std::vector<int32_t> p1 = agg;
+    for (int64_t i = 0; i < n; ++i) {   // phase 2
+        if (agg[i] >= 0) continue;
+        int64_t best = -1;
+        double ba = -1.0;
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+            if (!strong[e] || p1[A.ci[e]] < 0) continue;
+            const double a = std::fabs(A.va[e]);
+            if (best < 0 || a > ba * (1.0 + TIE_REL)) {
+                best = A.ci[e];
+                ba = a;
+            }
+        }
+        // a row left after phase 1 was blocked by a phase-1-aggregated strong
+        // neighbour, so best >= 0
+        agg[i] = best >= 0 ? p1[best] : (int32_t)nagg++;
+    }
+}
+
+double gershgorin(const HCsr &A, const std::vector<double> &d) {
+    double rho = 0.0;
+    for (int64_t i = 0; i < A.n; ++i) {
+        double s = 0.0;
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) s += std::fabs(A.va[e]);
+        rho = std::max(rho, s / d[i]);
+    }
+    return rho;
+}
+
+// Rows of a sparse matrix built row by row in parallel: cnt pass, then fill.
+template <typename RowFn>
+void build_rows(int64_t n, int64_t m, HCsr &out, RowFn &&row) {
+    out.n = n;
+    out.m = m;
+    out.rp.assign(n + 1, 0);
+    const int64_t CH = 4096;
+    const int64_t nch = (n + CH - 1) / CH;
+    std::vector<std::vector<int32_t>> cci(nch);
+    std::vector<std::vector<double>> cva(nch);
+    std::vector<std::vector<int32_t>> ccnt(nch);
+#pragma omp parallel
+    {
+        std::vector<std::pair<int32_t, double>> buf;
+        std::vector<double> acc(m, 0.0);
+        std::vector<int64_t> mark(m, -1);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t r0 = c * CH, r1 = std::min(n, r0 + CH);
+            ccnt[c].resize(r1 - r0);
+            for (int64_t i = r0; i < r1; ++i) {
+                buf.clear();
+                row(i, buf, acc, mark);
+                std::sort(buf.begin(), buf.end(),
+                          [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                              return a.first < b.first;
+                          });
+                ccnt[c][i - r0] = (int32_t)buf.size();
+                for (const auto &pv : buf) {
+                    cci[c].push_back(pv.first);
+                    cva[c].push_back(pv.second);
+                }
+            }
+        }
+    }
+    for (int64_t c = 0; c < nch; ++c)
+        for (size_t t = 0; t < ccnt[c].size(); ++t) out.rp[c * CH + t + 1] = ccnt[c][t];
+    for (int64_t i = 0; i < n; ++i) out.rp[i + 1] += out.rp[i];
+    out.ci.resize(out.rp[n]);
+    out.va.resize(out.rp[n]);
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t off = out.rp[c * CH];
+        std::copy(cci[c].begin(), cci[c].end(), out.ci.begin() + off);
+        std::copy(cva[c].begin(), cva[c].end(), out.va.begin() + off);
+    }
+}
+
+// P = (I - omega D^-1 A) P_t: row i holds the aggregates of the columns of
+// row i of A; entry a gets -omega/a_ii sum_{j in row i, agg(j) = a} a_ij t_a,
+// plus t_a at a = agg(i).
+void smoothed_p(const HCsr &A, const std::vector<double> &d, const std::vector<int32_t> &agg, int64_t nagg,
+                double omega, HCsr &P) {
+    std::vector<int64_t> cnt(nagg, 0);
+    for (int32_t a : agg) ++cnt[a];
+    std::vector<double> t(nagg);
+    for (int64_t a = 0; a < nagg; ++a) t[a] = 1.0 / std::sqrt((double)cnt[a]);
+    build_rows(A.n, nagg, P,
+               [&](int64_t i, std::vector<std::pair<int32_t, double>> &buf, std::vector<double> &acc,
+                   std::vector<int64_t> &mark) {
+                   for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+                       const int32_t a = agg[A.ci[e]];
+                       if (mark[a] != i) {
+                           mark[a] = i;
+                           acc[a] = 0.0;
+                           buf.push_back({a, 0.0});
+                       }
+                       acc[a] += A.va[e] * t[a];
+                   }
+                   const double s = -omega / d[i];
+                   for (auto &pv : buf) {
+                       pv.second = s * acc[pv.first];
+                       if (pv.first == agg[i]) pv.second += t[pv.first];
+                   }
+               });
+}
+
+void transpose(const HCsr &P, HCsr &R) {
+    R.n = P.m;
+    R.m = P.n;
+    R.rp.assign(R.n + 1, 0);
+    for (int64_t e = 0; e < P.nnz(); ++e) ++R.rp[P.ci[e] + 1];
+    for (int64_t i = 0; i < R.n; ++i) R.rp[i + 1] += R.rp[i];
+    R.ci.resize(P.nnz());
+    R.va.resize(P.nnz());
+    std::vector<int64_t> pos(R.rp.begin(), R.rp.end() - 1);
+    for (int64_t i = 0; i < P.n; ++i)   // rows in order: columns of R come out sorted
+        for (int32_t e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+            const int64_t q = pos[P.ci[e]]++;
+            R.ci[q] = (int32_t)i;
+            R.va[q] = P.va[e];
+        }
+}
+
+// C = A B (Gustavson, row by row; sums in the order of A's row and B's rows)
+void spgemm(const HCsr &A, const HCsr &B, HCsr &C) {
+    build_rows(A.n, B.m, C,
+               [&](int64_t i, std::vector<std::pair<int32_t, double>> &buf, std::vector<double> &acc,
+                   std::vector<int64_t> &mark) {
+                   for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+                       const double a = A.va[e];
+                       const int64_t k = A.ci[e];
+                       for (int32_t f = B.rp[k]; f < B.rp[k + 1]; ++f) {
+                           const int32_t c = B.ci[f];
+                           if (mark[c] != i) {
+                               mark[c] = i;
+                               acc[c] = 0.0;
+                               buf.push_back({c, 0.0});
+                           }
+                           acc[c] += a * B.va[f];
+                       }
+                   }
+                   for (auto &pv : buf) pv.second = acc[pv.first];
+               });
+}
+
+// Dense inverse of an SPD matrix through its Cholesky factor (row-major).
+bool spd_inverse(const HCsr &A, std::vector<double> &inv) {
+    const int64_t n = A.n;
+    std::vector<double> L((size_t)n * n, 0.0), M((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) M[(size_t)i * n + A.ci[e]] = A.va[e];
+    for (int64_t j = 0; j < n; ++j) {
+        double s = M[(size_t)j * n + j];
+        for (int64_t p = 0; p < j; ++p) s -= L[(size_t)j * n + p] * L[(size_t)j * n + p];
+        if (!(s > 0.0)) return false;
+        const double ljj = std::sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double v = M[(size_t)i * n + j];
+            for (int64_t p = 0; p < j; ++p) v -= L[(size_t)i * n + p] * L[(size_t)j * n + p];
+            L[(size_t)i * n + j] = v / ljj;
+        }
+    }
+    // Linv (lower) by forward substitution, inv = Linv^T Linv
+    std::vector<double> Li((size_t)n * n, 0.0);
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t i = c; i < n; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int64_t p = c; p < i; ++p) v -= L[(size_t)i * n + p] * Li[(size_t)p * n + c];
+            Li[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+        }
+    inv.assign((size_t)n * n, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int64_t p = std::max(i, j); p < n; ++p) s += Li[(size_t)p * n + i] * Li[(size_t)p * n + j];
+            inv[(size_t)i * n + j] = s;
+        }
+    return true;
+}
+
+hipError_t upload(std::vector<void *> &owned, void **dst, const void *src, size_t bytes) {
+    *dst = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    owned.push_back(*dst);
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+hipError_t upload_csr(std::vector<void *> &owned, const HCsr &H, DevCsr<double> &D) {
+    D.n = H.n;
+    D.nnz = H.nnz();
+    D.uorder = nullptr;
+    void *rp = nullptr, *ci = nullptr, *va = nullptr;
+    hipError_t e = upload(owned, &rp, H.rp.data(), sizeof(int32_t) * H.rp.size());
+    if (e == hipSuccess) e = upload(owned, &ci, H.ci.data(), sizeof(int32_t) * H.ci.size());
+    if (e == hipSuccess) e = upload(owned, &va, H.va.data(), sizeof(double) * H.va.size());
+    D.rowptr = (const int32_t *)rp;
+    D.colind = (const int32_t *)ci;
+    D.val = (const double *)va;
+    return e;
+}
+
+inline size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+void Amg::release() {
+    for (void *p : owned) (void)hipFree(p);
+    owned.clear();
+    if (work) (void)hipFree(work);
+    work = nullptr;
+    work_bytes = 0;
+    kcap = 0;
+    ldw = 0;
+    lv.clear();
+    cinv = nullptr;
+    agg.clear();
+    rows.clear();
+    nnz.clear();
+    omega.clear();
+    rho.clear();
+}
+
+int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStream_t st, std::string &err) {
+    release();
+    if (max_levels < 1 || max_levels > AMG_MAX_LEVELS || coarse_max < 1 || A0.n < 1) {
+        err = "amg: invalid setup parameters";
+        return GCGE_ERR_INVALID_ARG;
+    }
+    HCsr cur;
+    cur.n = cur.m = A0.n;
+    cur.rp.resize(A0.n + 1);
+    cur.ci.resize(A0.nnz);
+    cur.va.resize(A0.nnz);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(cur.rp.data(), A0.rowptr, sizeof(int32_t) * (A0.n + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && A0.nnz)
+        e = hipMemcpy(cur.ci.data(), A0.colind, sizeof(int32_t) * A0.nnz, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && A0.nnz)
+        e = hipMemcpy(cur.va.data(), A0.val, sizeof(double) * A0.nnz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        err = std::string("amg: download: ") + hipGetErrorString(e);
+        return status_of(e);
+    }
+    for (int lev = 0;; ++lev) {
+        std::vector<double> d;
+        if (!diag_of(cur, d)) {
+            err = "amg: the operator needs a positive diagonal at level " + std::to_string(lev);
+            release();
+            return GCGE_ERR_NOT_SPD;
+        }
+        AmgLevel L;
+        L.n = cur.n;
+        rows.push_back(cur.n);
+        nnz.push_back(cur.nnz());
+        if (lev == 0) {
+            L.A = A0;
+        } else {
+            e = upload_csr(owned, cur, L.A);
+        }
+        bool last = cur.n <= coarse_max || lev == max_levels - 1;
+        std::vector<int32_t> ag;
+        int64_t nagg = 0;
+        if (!last) {
+            aggregate(cur, d, STRENGTH_EPS0 * std::ldexp(1.0, -lev), ag, nagg);
+            if (nagg >= cur.n) last = true;
+        }
+        if (last) {
+            if (cur.n > AMG_COARSE_LIMIT) {
+                err = "amg: coarsest level has " + std::to_string(cur.n) + " rows (limit " +
+                      std::to_string(AMG_COARSE_LIMIT) + "); raise the level limit";
+                release();
+                return GCGE_ERR_INVALID_ARG;
+            }
+            std::vector<double> inv;
+            if (!spd_inverse(cur, inv)) {
+                err = "amg: coarsest operator is not positive definite";
+                release();
+                return GCGE_ERR_NOT_SPD;
+            }
+            void *p = nullptr;
+            if (e == hipSuccess) e = upload(owned, &p, inv.data(), sizeof(double) * inv.size());
+            cinv = (double *)p;
+            lv.push_back(L);
+            break;
+        }
+        const double r = gershgorin(cur, d);
+        const double om = 4.0 / (3.0 * r);
+        std::vector<double> w(cur.n);
+        for (int64_t i = 0; i < cur.n; ++i) w[i] = om / d[i];
+        void *pw = nullptr;
+        if (e == hipSuccess) e = upload(owned, &pw, w.data(), sizeof(double) * w.size());
+        L.w = (double *)pw;
+        HCsr P, R, AP, Ac;
+        smoothed_p(cur, d, ag, nagg, om, P);
+        transpose(P, R);
+        spgemm(cur, P, AP);
+        spgemm(R, AP, Ac);
+        if (e == hipSuccess) e = upload_csr(owned, P, L.P);
+        if (e == hipSuccess) e = upload_csr(owned, R, L.R);
+        if (e != hipSuccess) break;
+        agg.push_back(std::move(ag));
+        omega.push_back(om);
+        rho.push_back(r);
+        lv.push_back(L);
+        cur = std::move(Ac);
+    }
+    if (e != hipSuccess) {
+        err = std::string("amg: upload: ") + hipGetErrorString(e);
+        release();
+        return status_of(e);
+    }
+    return GCGE_OK;
+}
+
+int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
+               hipStream_t st, std::string &err) {
+    if (lv.empty()) {
+        err = "amg: no hierarchy";
+        return GCGE_ERR_INVALID_ARG;
+    }
+    if (k < 0 || k > 128 || ldb < k || ldy < k) {
+        err = "amg: invalid apply arguments";
+        return GCGE_ERR_INVALID_ARG;
+    }
+    if (nparts) *nparts = 0;
+    if (k == 0) return GCGE_OK;
+    hipError_t e = hipSuccess;
+    const int L = (int)lv.size() - 1;
+    if (k > kcap) {
+        // x, t on every smoothed level; b, y on every level but the finest
+        const int64_t ld = (k + 1) / 2 * 2;
+        size_t bytes = 0;
+        for (int l = 0; l <= L; ++l) {
+            const size_t v = pad256(sizeof(double) * lv[l].n * ld);
+            bytes += (l < L ? 2 * v : 0) + (l > 0 ? 2 * v : 0);
+        }
+        if (work) (void)hipFree(work);
+        work = nullptr;
+        work_bytes = 0;
+        kcap = 0;
+        e = hipMalloc((void **)&work, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            work = nullptr;
+            err = std::string("amg: work vectors: ") + hipGetErrorString(e);
+            return status_of(e);
+        }
+        work_bytes = bytes;
+        kcap = k;
+        ldw = ld;
+    }
+    // carve the work area (same layout for every k <= kcap)
+    std::vector<double *> X(L + 1, nullptr), T(L + 1, nullptr), Bv(L + 1, nullptr), Y(L + 1, nullptr);
+    {
+        char *p = (char *)work;
+        for (int l = 0; l <= L; ++l) {
+            const size_t v = pad256(sizeof(double) * lv[l].n * ldw);
+            if (l < L) {
+                X[l] = (double *)p;
+                T[l] = (double *)(p + v);
+                p += 2 * v;
+            }
+            if (l > 0) {
+                Bv[l] = (double *)p;
+                Y[l] = (double *)(p + v);
+                p += 2 * v;
+            }
+        }
+    }
+    // descend: pre-smoothing, residual, restriction
+    const double *bl = b;
+    int64_t ldbl = ldb;
+    for (int l = 0; l < L && e == hipSuccess; ++l) {
+        const AmgLevel &V = lv[l];
+        e = scale_rows(V.n, k, V.w, bl, ldbl, X[l], ldw, st);
+        Affine<double> res;
+        res.b = bl;
+        res.ldb = ldbl;
+        if (e == hipSuccess) e = spmm_affine<double>(V.A, X[l], ldw, k, T[l], ldw, res, st);
+        if (e == hipSuccess)
+            e = spmm<double>(V.R, nullptr, nullptr, nullptr, 0, 0, T[l], ldw, k, Bv[l + 1], ldw, nullptr, 0,
+                             nullptr, nullptr, st);
+        bl = Bv[l + 1];
+        ldbl = ldw;
+    }
+    // coarsest level: y_L = A_L^-1 b_L
+    if (e == hipSuccess) {
+        const int64_t nc = lv[L].n;
+        double *yL = L == 0 ? y : Y[L];
+        const int64_t ldyL = L == 0 ? ldy : ldw;
+        Segs S;
+        S.add(cinv, nc, (int)nc);
+        e = gemm(nc, S, bl, ldbl, k, 1.0, 0.0, yL, ldyL, st);
+        if (L == 0 && part != nullptr && e == hipSuccess) e = coldot_part(nc, k, y, ldy, b, ldb, part, nparts, st);
+    }
+    // ascend: coarse correction, post-smoothing
+    for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
+        const AmgLevel &V = lv[l];
+        const double *bb = l == 0 ? b : Bv[l];
+        const int64_t ldbb = l == 0 ? ldb : ldw;
+        Affine<double> cor;
+        cor.z = X[l];
+        cor.ldz = ldw;
+        cor.ws = -1.0;
+        e = spmm_affine<double>(V.P, Y[l + 1], ldw, k, X[l], ldw, cor, st);
+        Affine<double> sm;
+        sm.b = bb;
+        sm.ldb = ldbb;
+        sm.z = X[l];
+        sm.ldz = ldw;
+        sm.w = V.w;
+        sm.ws = 1.0;
+        double *out = l == 0 ? y : Y[l];
+        const int64_t ldo = l == 0 ? ldy : ldw;
+        if (e == hipSuccess) {
+            if (l == 0 && part != nullptr)
+                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, b, ldb, part, nparts);
+            else
+                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st);
+        }
+    }
+    if (e != hipSuccess) {
+        err = std::string("amg: V-cycle: ") + hipGetErrorString(e);
+        return status_of(e);
+    }
+    return GCGE_OK;
+}
+
+}  // namespace gcge

@@ -83,6 +83,27 @@ int max_row_parts();
 // red = 0: none; red = 1: partial sums of y^2 and (Bx)^2 per column into part
 // (layout [2][k][nparts]); red = 2: partial sums of z_j . y_j (layout [k][nparts]).
 // *nparts receives the number of partials per column (the launch's grid).
+// Operands of the affine SpMM epilogue: row i of the output is
+// z_i + w_i (b_i - (A x)_i) with w_i = ws * w[i] (ws when w is null); a null b
+// or z reads as zero.  The multigrid V-cycle uses it for the residual
+// (z = 0, w = 1), the damped Jacobi sweep (z = x, w = omega / a_ii) and the
+// coarse-grid correction (A = P, b = 0, z = x, w = -1, in place).
+template <typename T>
+struct Affine {
+    const T *b = nullptr;
+    int64_t ldb = 0;
+    const T *z = nullptr;
+    int64_t ldz = 0;
+    const T *w = nullptr;
+    T ws = T(1);
+};
+// With zdot != nullptr the SpMM also writes partials of the column dots
+// y . zdot (part[c * np + g], np in *nparts), as the RED = 2 products do.
+template <typename T>
+hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const Affine<T> &af,
+                       hipStream_t st, const T *zdot = nullptr, int64_t ldzdot = 0, T *part = nullptr,
+                       int *nparts = nullptr);
+
 template <typename T>
 hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, int mode, int red,
                 const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part,
@@ -97,6 +118,7 @@ template <typename T>
 struct CgState {
     T *rr, *rr0, *alpha, *beta;
     int *active, *its, *flags;   // flags[0] = columns still iterating, flags[1] = columns updated this iteration
+    T *rz = nullptr;             // preconditioned CG: r . z per column (alpha = rz / pq, beta = rz_new / rz)
 };
 
 template <typename T>
@@ -113,6 +135,16 @@ template <typename T>
 hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> cs, hipStream_t st);
 template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st);
+// Y = diag(d) X (n x k row-major).
+hipError_t scale_rows(int64_t n, int k, const double *d, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                      hipStream_t st);
+// Preconditioned CG: rz[c] = sum of the partials (init: beta = 0), or, for the
+// columns updated this iteration, beta = rz_new / rz and rz = rz_new.
+template <typename T>
+hipError_t pcg_rz(const T *part, int nparts, int k, bool init, CgState<T> cs, hipStream_t st);
+// Partials of the column dots x[:, c] . y[:, c] (part[c * np + g], np in *nparts).
+hipError_t coldot_part(int64_t n, int k, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
+                       int *nparts, hipStream_t st);
 // SpMM of the CG iteration (q = M p with partial p.q), skipped when flags[0] == 0.
 template <typename T>
 hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int *nparts,
@@ -172,6 +204,40 @@ struct DenseEigWork {
 // nwant row-major, ldx) with X^T X = I.  Asynchronous on st.
 hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, double *X, int64_t ldx,
                      DenseEigWork &dw, Workspace &ws, hipStream_t st);
+
+// ------------------------------------------------------- multigrid (STEP 6)
+// Smoothed-aggregation algebraic multigrid for the STEP 6 systems at theta = 0
+// (Section 2 suggests an algebraic multigrid preconditioner there).  The
+// hierarchy is built on the host; the V-cycle runs on the device.
+struct AmgLevel {
+    int64_t n = 0;
+    DevCsr<double> A, P, R;   // level operator, prolongator (n x n_next), restriction P^T
+    double *w = nullptr;      // omega / a_ii of the damped Jacobi sweep
+};
+struct Amg {
+    std::vector<AmgLevel> lv;                 // the last level is solved with cinv
+    double *cinv = nullptr;                   // dense inverse of the coarsest operator (row-major)
+    std::vector<void *> owned;                // device arrays of the hierarchy
+    std::vector<std::vector<int32_t>> agg;    // aggregate of each row, per coarsened level
+    std::vector<int64_t> rows, nnz;
+    std::vector<double> omega, rho;
+    double *work = nullptr;                   // V-cycle vectors for up to kcap columns
+    size_t work_bytes = 0;
+    int kcap = 0;
+    int64_t ldw = 0;
+    // A0: device CSR of the level-0 operator (borrowed; must outlive the hierarchy).
+    int build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStream_t st, std::string &err);
+    // y = V(b) for k <= 128 columns (b and y n x k row-major, 16-byte aligned
+    // rows when ldb, ldy are even).  With part != nullptr the last kernel also
+    // writes per-work-group partials of the column dots b . y (part[c * np + g],
+    // np in *nparts).
+    int apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
+              hipStream_t st, std::string &err);
+    void release();
+    ~Amg() { release(); }
+};
+constexpr int AMG_MAX_LEVELS = 16;
+constexpr int64_t AMG_COARSE_LIMIT = 4096;   // largest coarsest level (dense inverse)
 
 // ------------------------------------------------------------- host dense
 // Symmetric eigensolver: a (n x n, row-major, destroyed), w ascending, z (n x

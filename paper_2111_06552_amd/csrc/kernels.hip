@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
                                               const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
                                               int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
                                               int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
-                                              const int *__restrict__ skip) {
+                                              const int *__restrict__ skip, Affine<T> af) {
     if (skip != nullptr && skip[0] == 0) return;
     constexpr int NG = 256 / G;
     const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
@@ -184,6 +184,11 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
             } else if (MODE == 2) {
                 bx = accb[t];
                 y = fma(-sg[t], bx, y);
+            } else if (MODE == 3) {
+                const T w = af.w != nullptr ? af.ws * af.w[row] : af.ws;
+                const T bb = af.b != nullptr ? af.b[row * af.ldb + col[t]] : T(0);
+                const T zz = af.z != nullptr ? af.z[row * af.ldz + col[t]] : T(0);
+                y = fma(w, bb - y, zz);
             }
             Y[row * ldy + col[t]] = y;
             if (RED == 1) {
@@ -236,129 +241,18 @@ __device__ __forceinline__ void vst_nt(T *p, const Vec<T, V> &x) {
     for (int v = 0; v < V; ++v) __builtin_nontemporal_store(x.v[v], p + v);
 }
 
-// SpMM with 16-byte vector accesses: a group of G lanes per row, lane l owns
-// columns V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 8,
-// all eight gathered vector rows being requested before they are used.
-// Requires 16-byte aligned rows and leading dimensions that cover
-// round_up(k, V) columns (the tail lane may touch padding columns, which are
-// never part of a reduction).
-template <typename T, int G, int V, int MODE, int RED>
-__global__ __launch_bounds__(256) void k_spmmv(int64_t n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ colind, const T *__restrict__ va,
-                                               const T *__restrict__ vb, const T *__restrict__ dg,
-                                               const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
-                                               int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
-                                               int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
-                                               const int *__restrict__ skip) {
-    if (skip != nullptr && skip[0] == 0) return;
-    constexpr int NG = 256 / G, U = 8;
-    const int tid = threadIdx.x, grp = tid / G, lig = tid % G;
-    const int chunk = blockIdx.x;
-    const RowWalk rw = row_walk(n, NG);
-    const int c0 = lig * V;
-    const bool on = c0 < k;
-    T sg[V], red1[V], red2[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        sg[v] = (MODE != 0 && c0 + v < k) ? sigma[c0 + v] : T(0);
-        red1[v] = red2[v] = T(0);
-    }
-    for (int64_t base = rw.first; base < rw.end; base += rw.stride) {
-        const int64_t row = base + grp;
-        if (row >= rw.end) break;
-        const int e0 = rowptr[row], e1 = rowptr[row + 1];
-        Vec<T, V> acc, accb;
-#pragma unroll
-        for (int v = 0; v < V; ++v) acc.v[v] = accb.v[v] = T(0);
-        for (int e = e0; e < e1; e += U) {
-            int cc[U];
-            T av[U], bv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = e + u < e1;
-                cc[u] = ok ? colind[e + u] : (int)row;
-                av[u] = ok ? va[e + u] : T(0);
-                bv[u] = (MODE == 2 && ok) ? vb[e + u] : T(0);
-            }
-            Vec<T, V> xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (on) {
-                    xv[u] = vld<T, V>(X + (int64_t)cc[u] * ldx + c0);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) xv[u].v[v] = T(0);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    acc.v[v] = fma(av[u], xv[u].v[v], acc.v[v]);
-                    if (MODE == 2) accb.v[v] = fma(bv[u], xv[u].v[v], accb.v[v]);
-                }
-        }
-        if (!on) continue;
-        T bx[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) bx[v] = T(0);
-        if (MODE == 1) {
-            const Vec<T, V> xs = vld<T, V>(X + row * ldx + c0);
-            const T dw = (dg != nullptr) ? dg[row] : T(1);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                bx[v] = dw * xs.v[v];
-                acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
-            }
-        } else if (MODE == 2) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                bx[v] = accb.v[v];
-                acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
-            }
-        }
-        vst<T, V>(Y + row * ldy + c0, acc);
-        if (RED == 1) {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (c0 + v < k) {
-                    red1[v] = fma(acc.v[v], acc.v[v], red1[v]);
-                    red2[v] = fma(bx[v], bx[v], red2[v]);
-                }
-        } else if (RED == 2) {
-            const Vec<T, V> z = vld<T, V>(Z + row * ldz + c0);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (c0 + v < k) red1[v] = fma(acc.v[v], z.v[v], red1[v]);
-        }
-    }
-    if (RED != 0) {
-        __shared__ T sh[2][NG][G * V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            sh[0][grp][c0 + v] = red1[v];
-            sh[1][grp][c0 + v] = red2[v];
-        }
-        __syncthreads();
-        for (int c = tid; c < G * V; c += 256) {
-            if (c >= k) continue;
-            T s1 = T(0), s2 = T(0);
-            for (int g = 0; g < NG; ++g) {
-                s1 += sh[0][g][c];
-                s2 += sh[1][g][c];
-            }
-            part[(size_t)c * gridDim.x + chunk] = s1;
-            if (RED == 1) part[(size_t)(k + c) * gridDim.x + chunk] = s2;
-        }
-    }
-}
-
 // SpMM with the sparsity pattern of each block of RS consecutive rows staged
 // in LDS: the work-group loads the block's row pointers, then its column
 // indices and values with one coalesced sweep, and the row groups gather the
 // vector rows with the indices read from LDS (no per-lane broadcast loads,
 // one dependent global round trip per row instead of three).  Blocks whose
 // nonzeros do not fit the staging area fall back to global index loads.
+// 16-byte vector accesses: a group of G lanes per row, lane l owns columns
+// V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 8, all eight
+// gathered vector rows being requested before they are used.  Requires
+// 16-byte aligned rows and leading dimensions that cover round_up(k, V)
+// columns: the tail lane reads padding columns of the inputs (never part of a
+// result) but writes only the columns below k.
 template <typename T, int G, int V, int MODE, int RED>
 __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ colind, const T *__restrict__ va,
@@ -366,7 +260,8 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                                                const T *__restrict__ sigma, const T *__restrict__ X, int64_t ldx,
                                                int k, T *__restrict__ Y, int64_t ldy, const T *__restrict__ Z,
                                                int64_t ldz, T *__restrict__ part, int nparts, int64_t rows_per,
-                                               const int *__restrict__ skip, const int32_t *__restrict__ uorder) {
+                                               const int *__restrict__ skip, const int32_t *__restrict__ uorder,
+                                               Affine<T> af) {
     if (skip != nullptr && skip[0] == 0) return;
     constexpr int NG = 256 / G, U = 8;
     constexpr int RS = NG > 32 ? NG : 32;   // rows per staged block (divides 64)
@@ -479,8 +374,23 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                     bx[v] = accb.v[v];
                     acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
                 }
+            } else if (MODE == 3) {
+                const T w = af.w != nullptr ? af.ws * af.w[row] : af.ws;
+                Vec<T, V> bb, zz;
+#pragma unroll
+                for (int v = 0; v < V; ++v) bb.v[v] = zz.v[v] = T(0);
+                if (af.b != nullptr) bb = vld<T, V>(af.b + row * af.ldb + c0);
+                if (af.z != nullptr) zz = vld<T, V>(af.z + row * af.ldz + c0);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc.v[v] = fma(w, bb.v[v] - acc.v[v], zz.v[v]);
             }
-            vst_nt<T, V>(Y + row * ldy + c0, acc);
+            if (c0 + V <= k) {
+                vst_nt<T, V>(Y + row * ldy + c0, acc);
+            } else {   // tail lane: the padding columns of Y are left untouched
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (c0 + v < k) Y[row * ldy + c0 + v] = acc.v[v];
+            }
             if (RED == 1) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
@@ -526,13 +436,15 @@ static inline bool aligned16(const T *p) {
 template <typename T, int MODE, int RED>
 static hipError_t spmm_dispatch(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, const T *X,
                                 int64_t ldx, int k, T *Y, int64_t ldy, const T *Z, int64_t ldz, T *part,
-                                int *nparts, const int *skip, hipStream_t st) {
+                                int *nparts, const int *skip, hipStream_t st, const Affine<T> &af = Affine<T>{}) {
     dim3 block(256);
     constexpr int V = 16 / sizeof(T);
     const int kp = (k + V - 1) / V * V;
     const bool vec = aligned16(X) && aligned16(Y) && aligned16(Z) && ldx % V == 0 && ldy % V == 0 &&
                      (Z == nullptr || ldz % V == 0) && kp <= ldx && kp <= ldy && (Z == nullptr || kp <= ldz) &&
-                     kp <= 64 * V;
+                     kp <= 64 * V && aligned16(af.b) && aligned16(af.z) &&
+                     (af.b == nullptr || (af.ldb % V == 0 && kp <= af.ldb)) &&
+                     (af.z == nullptr || (af.ldz % V == 0 && kp <= af.ldz));
     const void *fn = nullptr;
     int units = 1;
     if (vec) {
@@ -547,7 +459,7 @@ static hipError_t spmm_dispatch(const DevCsr<T> &A, const T *vb, const T *dg, co
         if (nparts) *nparts = g;                                                                         \
         hipLaunchKernelGGL((k_spmms<T, Gv, V, MODE, RED>), dim3(g), block, 0, st, A.n, A.rowptr, A.colind, \
                            A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip,      \
-                           A.uorder);                                                                   \
+                           A.uorder, af);                                                               \
     }
         GCGE_SPMMS(4) else GCGE_SPMMS(8) else GCGE_SPMMS(16) else GCGE_SPMMS(32) else GCGE_SPMMS(64)
 #undef GCGE_SPMMS
@@ -562,7 +474,7 @@ static hipError_t spmm_dispatch(const DevCsr<T> &A, const T *vb, const T *dg, co
         const int g = resident_grid(fn, units);                                                          \
         if (nparts) *nparts = g;                                                                         \
         hipLaunchKernelGGL((k_spmm<T, Gv, CTv, MODE, RED>), dim3(g), block, 0, st, A.n, A.rowptr, A.colind, \
-                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip);     \
+                           A.val, vb, dg, sigma, X, ldx, k, Y, ldy, Z, ldz, part, g, (int64_t)0, skip, af); \
     }
     GCGE_SPMM1(16, 1) else GCGE_SPMM1(32, 1) else GCGE_SPMM1(64, 1) else GCGE_SPMM1(64, 2)
 #undef GCGE_SPMM1
@@ -618,6 +530,24 @@ template hipError_t cg_spmm<double>(const DevCsr<double> &, const double *, doub
                                     const int *, hipStream_t);
 template hipError_t cg_spmm<float>(const DevCsr<float> &, const float *, float *, int64_t, int, float *, int *,
                                    const int *, hipStream_t);
+
+template <typename T>
+hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const Affine<T> &af,
+                       hipStream_t st, const T *zdot, int64_t ldzdot, T *part, int *nparts) {
+    if (nparts) *nparts = 0;
+    if (A.n == 0 || k == 0) return hipSuccess;
+    if (k > 128) return hipErrorInvalidValue;
+    if (zdot != nullptr) {
+        if (part == nullptr || nparts == nullptr) return hipErrorInvalidValue;
+        return spmm_dispatch<T, 3, 2>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, zdot, ldzdot, part, nparts,
+                                      nullptr, st, af);
+    }
+    return spmm_dispatch<T, 3, 0>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, nullptr, 0, nullptr, nullptr,
+                                  nullptr, st, af);
+}
+template hipError_t spmm_affine<double>(const DevCsr<double> &, const double *, int64_t, int, double *, int64_t,
+                                        const Affine<double> &, hipStream_t, const double *, int64_t, double *,
+                                        int *);
 
 // ---------------------------------------------------------------------------
 // fixed-order column sums of partials (one work-group, 16 waves)
@@ -727,7 +657,7 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t n, int k, const double 
 
 
 // Vector forms of the two CG update passes (16-byte accesses; same layout
-// conditions as k_spmmv).
+// conditions as k_spmms).
 template <typename T, int G, int V>
 __global__ __launch_bounds__(256) void k_cg_update_r_v(int64_t n, int k, const T *__restrict__ q,
                                                        T *__restrict__ r, int64_t ld, T *__restrict__ part,
@@ -948,7 +878,7 @@ __global__ __launch_bounds__(1024) void k_cg_alpha(const T *__restrict__ part, i
                 T al = T(0);
                 if (cs.active[c]) {
                     if (pq > T(0)) {
-                        al = cs.rr[c] / pq;
+                        al = (cs.rz != nullptr ? cs.rz[c] : cs.rr[c]) / pq;
                         cs.its[c] += 1;
                     } else {
                         cs.active[c] = 0;   // p^T (A - theta B) p <= 0: freeze the column
@@ -989,7 +919,7 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const T *__restrict__ part, in
                     cs.rr[c] = rrn;
                     if (rrn <= tol2 * cs.rr0[c]) cs.active[c] = 0;
                 }
-                cs.beta[c] = be;
+                if (cs.rz == nullptr) cs.beta[c] = be;   // preconditioned: beta comes from r . z
             }
     }
     __syncthreads();
@@ -997,6 +927,55 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const T *__restrict__ part, in
         int na = 0;
         for (int c = 0; c < k; ++c) na += cs.active[c];
         cs.flags[0] = na;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pcg_rz(const T *__restrict__ part, int nparts, int k, int init,
+                                                 CgState<T> cs) {
+    if (!init && cs.flags[1] == 0) return;
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int c0 = 0; c0 < k; c0 += 128) {
+        T sums[8];
+        colsums_wave(part, nparts, k, c0, w, lane, sums);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = c0 + w + 16 * i;
+                if (c >= k) continue;
+                const T s = sums[i];
+                if (init) {
+                    cs.rz[c] = s;
+                    cs.beta[c] = T(0);
+                } else if (cs.alpha[c] != T(0)) {
+                    cs.beta[c] = s / cs.rz[c];
+                    cs.rz[c] = s;
+                } else {
+                    cs.beta[c] = T(0);
+                }
+            }
+    }
+}
+
+// Column-dot partials: 64 lanes per row (two columns each), 4 rows per
+// work-group step; the four row groups are summed in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_coldot_part(int64_t n, int k, const double *__restrict__ X, int64_t ldx,
+                                                     const double *__restrict__ Y, int64_t ldy,
+                                                     double *__restrict__ part) {
+    const int tid = threadIdx.x, grp = tid / 64, lane = tid % 64;
+    double s0 = 0.0, s1 = 0.0;
+    const int c0 = lane, c1 = lane + 64;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + grp; r < n; r += (int64_t)gridDim.x * 4) {
+        if (c0 < k) s0 = fma(X[r * ldx + c0], Y[r * ldy + c0], s0);
+        if (c1 < k) s1 = fma(X[r * ldx + c1], Y[r * ldy + c1], s1);
+    }
+    __shared__ double sh[4][128];
+    sh[grp][c0] = s0;
+    sh[grp][c1] = s1;
+    __syncthreads();
+    if (tid < 128 && tid < k) {
+        const double v = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
+        part[(size_t)tid * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -1104,6 +1083,23 @@ hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, Cg
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t pcg_rz(const T *part, int nparts, int k, bool init, CgState<T> cs, hipStream_t st) {
+    if (k > 128 || cs.rz == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pcg_rz<T>, dim3(1), dim3(1024), 0, st, part, nparts, k, init ? 1 : 0, cs);
+    return hipGetLastError();
+}
+template hipError_t pcg_rz<double>(const double *, int, int, bool, CgState<double>, hipStream_t);
+
+hipError_t coldot_part(int64_t n, int k, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
+                       int *nparts, hipStream_t st) {
+    if (k < 1 || k > 128 || n < 1) return hipErrorInvalidValue;
+    const int g = (int)std::min<int64_t>((n + 3) / 4, (int64_t)max_row_parts());
+    hipLaunchKernelGGL(k_coldot_part, dim3(g), dim3(256), 0, st, n, k, X, ldx, Y, ldy, part);
+    *nparts = g;
+    return hipGetLastError();
 }
 
 #define GCGE_CG_INST(T)                                                                                          \

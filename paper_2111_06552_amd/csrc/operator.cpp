@@ -12,8 +12,6 @@
 namespace gcge {
 
 hipError_t scatter_values(int64_t nnz, const int32_t *map, const double *src, double *dst, hipStream_t st);
-hipError_t scale_rows(int64_t n, int k, const double *d, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                      hipStream_t st);
 
 #define GCGE_TRY(expr)                           \
     do {                                         \

@@ -165,6 +165,63 @@ struct CgRunner {
         if (total_its) *total_its += it;
         return GCGE_OK;
     }
+    // Preconditioned CG (M^-1 = the multigrid V-cycle) on M delta = R, delta
+    // from 0; same stopping rule as run().  z is one more n x ld vector.
+    int run_pcg(const DevCsr<T> &M, Amg &amg, const double *R, int64_t ldr, int k, int maxit, double rel_tol, T *x,
+                T *r, T *p, T *q, T *z, int64_t ld, CgState<T> cs, int64_t *total_its) {
+        static_assert(sizeof(T) == sizeof(double), "the V-cycle is FP64");
+        hipError_t e = ws.ensure_part(sizeof(double) * (size_t)k * max_row_parts() + 256);
+        if (e != hipSuccess) return fail(e, "workspace");
+        T *part = (T *)ws.part;
+        int nparts = 0;
+        e = cg_init<T>(R, ldr, nullptr, k, n, r, p, x, ld, part, &nparts, cs, st);
+        if (e == hipSuccess) e = cg_init_finish<T>(part, nparts, k, cs, st);
+        if (e != hipSuccess) return fail(e, "pcg init");
+        int rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err);
+        if (rc) return rc;
+        e = pcg_rz<T>(part, nparts, k, true, cs, st);
+        if (e == hipSuccess) e = copy_cols<T, T>(n, k, z, ld, p, ld, nullptr, st);
+        if (e != hipSuccess) return fail(e, "pcg init");
+        bool pending = false;
+        int it = 0;
+        for (; it < maxit; ++it) {
+            int pb = prof ? prof->begin(st) : -1;
+            e = cg_spmm<T>(M, p, q, ld, k, part, &nparts, cs.flags, st);
+            if (prof) prof->end(0, pb, k, st);
+            if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
+            pb = prof ? prof->begin(st) : -1;
+            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, cs, st);
+            if (prof) prof->end(1, pb, k, st);
+            if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
+            if (e != hipSuccess) return fail(e, "pcg iteration");
+            pb = prof ? prof->begin(st) : -1;
+            rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err);
+            if (prof) prof->end(6, pb, k, st);
+            if (rc) return rc;
+            e = pcg_rz<T>(part, nparts, k, false, cs, st);
+            pb = prof ? prof->begin(st) : -1;
+            if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, z, ld, cs, st);
+            if (prof) prof->end(2, pb, k, st);
+            if (e != hipSuccess) return fail(e, "pcg iteration");
+            if (pinned_flag != nullptr && (it % 2) == 1) {
+                if (pending && hipEventQuery(ev) == hipSuccess) {
+                    pending = false;
+                    if (*pinned_flag == 0) {
+                        ++it;
+                        break;
+                    }
+                }
+                if (!pending) {
+                    e = hipMemcpyAsync(pinned_flag, cs.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+                    if (e == hipSuccess) e = hipEventRecord(ev, st);
+                    if (e != hipSuccess) return fail(e, "pcg poll");
+                    pending = true;
+                }
+            }
+        }
+        if (total_its) *total_its += it;
+        return GCGE_OK;
+    }
     int fail(hipError_t e, const char *what) {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return hip_status(e);
@@ -183,6 +240,10 @@ struct gcge_handle_s {
     // options
     int64_t opt_bs = 0, opt_sizex = 0;
     int max_iter = 1000, cg_max_iter = 30, precision = GCGE_PREC_FP64, moving = 0, shift = 1, check = 1;
+    int precond = 0, amg_levels = 10, amg_coarse = 512;   // STEP 6 preconditioner (1: multigrid at theta = 0)
+    Amg amg;
+    bool amg_valid = false;
+    double amg_setup_ms = 0.0;
     uint64_t seed = 1;
     double cg_rel_tol = 1e-2, orth_tol = 1e-13, drop_tol = 1e-8;
     hipStream_t st = nullptr;
@@ -202,7 +263,7 @@ struct gcge_handle_s {
     double *Pb[2] = {nullptr, nullptr};
     double *Wb = nullptr, *AWb = nullptr, *BWb = nullptr, *Rb = nullptr;
     int64_t ldB = 0;
-    double *cg64[3] = {nullptr, nullptr, nullptr};
+    double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};
     float *cg32[4] = {nullptr, nullptr, nullptr, nullptr};
     void *cgmem = nullptr;
     double *mval = nullptr;
@@ -308,8 +369,8 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
     A((void **)&Rb, sizeof(double) * n * ldB);
     if (op.bkind == GCGE_B_CSR) A((void **)&BWb, sizeof(double) * n * ldB);
     A((void **)&mval, sizeof(double) * std::max<int64_t>(op.nnz, 1));
-    if (prec == GCGE_PREC_FP64) {
-        for (int i = 0; i < 3; ++i) A((void **)&cg64[i], sizeof(double) * n * ldB);
+    if (prec % 2 == GCGE_PREC_FP64) {
+        for (int i = 0; i < (prec >= 2 ? 4 : 3); ++i) A((void **)&cg64[i], sizeof(double) * n * ldB);
     } else {
         A((void **)&mval32, sizeof(float) * std::max<int64_t>(op.nnz, 1));
         for (int i = 0; i < 4; ++i) A((void **)&cg32[i], sizeof(float) * n * ldB);
@@ -396,6 +457,18 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
                            (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
         CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
         DevCsr<double> M = op.csr_of(mval);
+        if (precond) {
+            if (!amg_valid) {
+                const auto ta = Clock::now();
+                int rc = amg.build(op.A_csr(), amg_levels, amg_coarse, st, err);
+                if (rc) return rc;
+                amg_valid = true;
+                amg_setup_ms = ms_since(ta);
+            }
+            cs.rz = (double *)(cm + 7 * slot);
+            return runner.run_pcg(M, amg, Rb, ldB, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2],
+                                  cg64[3], ldB, cs, cg_its);
+        }
         return runner.run(M, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
                           cg_its);
     }
@@ -443,7 +516,9 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     const int sizeX = (int)sx;
     const int nx0 = mv ? (int)std::min<int64_t>(3 * (int64_t)bs, n) : sizeX;
     if (x0_k > nx0) return fail(GCGE_ERR_INVALID_ARG, "more initial vectors than the initial block holds");
-    int rc = ensure_buffers(bs, nx0, precision);
+    if (precond && precision != GCGE_PREC_FP64)
+        return fail(GCGE_ERR_INVALID_ARG, "the multigrid preconditioner runs with precision fp64");
+    int rc = ensure_buffers(bs, nx0, precision + 2 * precond);
     if (rc) return rc;
     stg.st = st;
     hipError_t e;
@@ -579,7 +654,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         // ---------------- STEP 6: inner CG with the dynamic shift
         auto t6 = Clock::now();
         double theta = 0.0;
-        if (shift && ell > 0) theta = *std::max_element(lam_lock.begin(), lam_lock.begin() + ell);
+        if (shift && !precond && ell > 0) theta = *std::max_element(lam_lock.begin(), lam_lock.begin() + ell);
         int64_t cgi = 0;
         rc = do_cg(theta, bsa2, rn, &cgi);
         if (rc) return rc;
@@ -802,6 +877,16 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "dense_eig") { if (v != 0 && v != 1) return bad(); h->dense_eig_opt = (int)v; }
     else if (k == "orth") { if (v != 2 && v != 3) return bad(); h->orth_alg = (int)v; }
     else if (k == "orth_block") { if (v < 0 || v > 100000) return bad(); h->orth_block_opt = (int)v; }
+    else if (k == "precond") { if (v != 0 && v != 1) return bad(); h->precond = (int)v; }
+    else if (k == "amg_levels") {
+        if (v < 1 || v > AMG_MAX_LEVELS) return bad();
+        h->amg_levels = (int)v;
+        h->amg_valid = false;
+    } else if (k == "amg_coarse") {
+        if (v < 1 || v > AMG_COARSE_LIMIT) return bad();
+        h->amg_coarse = (int)v;
+        h->amg_valid = false;
+    }
     else return h->fail(GCGE_ERR_INVALID_ARG, "unknown option " + k);
     return GCGE_OK;
 }
@@ -848,6 +933,7 @@ extern "C" int gcge_solve(gcge_handle h, double *evals, double *evecs, int64_t l
 extern "C" int gcge_update_values(gcge_handle h, const double *a_val, const void *b_val) {
     if (!h) return GCGE_ERR_INVALID_ARG;
     h->m_valid = h->m32_valid = false;
+    h->amg_valid = false;
     h->have_res = false;
     std::string err;
     int rc = h->op.set_values(a_val, b_val, h->st, err);
@@ -893,6 +979,7 @@ extern "C" void gcge_destroy(gcge_handle h) {
     if (h->st) (void)hipStreamSynchronize(h->st);
     else (void)hipDeviceSynchronize();
     h->bufs.release();
+    h->amg.release();
     h->op.destroy();
     h->ws.release();
     h->stg.release();
@@ -1174,6 +1261,123 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
         return GCGE_OK;
     } catch (...) {
         return step_fail(GCGE_ERR_INTERNAL, "gcge_cg: internal error");
+    }
+}
+
+struct gcge_amg_s {
+    Amg amg;
+    std::mutex mu;
+    std::string err;
+};
+
+extern "C" int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, void *stream, gcge_amg *out) {
+    if (!out) return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_create: out is null");
+    *out = nullptr;
+    if (!A || !csr_ok(A) || max_levels < 1 || max_levels > AMG_MAX_LEVELS || coarse_max < 1 ||
+        coarse_max > AMG_COARSE_LIMIT)
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_create: invalid argument");
+    try {
+        gcge_amg_s *h = new gcge_amg_s;
+        const int rc = h->amg.build(to_dev(A), max_levels, coarse_max, (hipStream_t)stream, h->err);
+        if (rc) {
+            const std::string m = h->err;
+            delete h;
+            return step_fail(rc, m);
+        }
+        *out = h;
+        return GCGE_OK;
+    } catch (...) {
+        return step_fail(GCGE_ERR_INTERNAL, "gcge_amg_create: internal error");
+    }
+}
+
+extern "C" int gcge_amg_levels(gcge_amg h, int *nlevels, int64_t *rows, int64_t *nnz, int cap) {
+    if (!h || !nlevels || cap < 0 || (cap > 0 && (!rows || !nnz)))
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_levels: invalid argument");
+    const int nl = (int)h->amg.lv.size();
+    *nlevels = nl;
+    for (int l = 0; l < std::min(nl, cap); ++l) {
+        rows[l] = h->amg.rows[l];
+        nnz[l] = h->amg.nnz[l];
+    }
+    return GCGE_OK;
+}
+
+extern "C" int gcge_amg_aggregates(gcge_amg h, int level, int32_t *agg) {
+    if (!h || !agg || level < 0 || level >= (int)h->amg.agg.size())
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_aggregates: invalid argument");
+    std::memcpy(agg, h->amg.agg[level].data(), sizeof(int32_t) * h->amg.agg[level].size());
+    return GCGE_OK;
+}
+
+extern "C" int gcge_amg_apply(gcge_amg h, const double *B, int64_t ldb, int k, double *Y, int64_t ldy, void *stream) {
+    if (!h || k < 0 || k > 128 || (k > 0 && (!B || !Y || ldb < k || ldy < k)))
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_apply: invalid argument");
+    if (k == 0) return GCGE_OK;
+    try {
+        std::lock_guard<std::mutex> lk(h->mu);
+        hipStream_t st = (hipStream_t)stream;
+        const int rc = h->amg.apply(B, ldb, k, Y, ldy, nullptr, nullptr, st, h->err);
+        if (rc) return step_fail(rc, h->err);
+        return GCGE_OK;
+    } catch (...) {
+        return step_fail(GCGE_ERR_INTERNAL, "gcge_amg_apply: internal error");
+    }
+}
+
+extern "C" void gcge_amg_destroy(gcge_amg h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+extern "C" int gcge_pcg(const gcge_csr *A, gcge_amg M, const double *R, int64_t ldr, int k, int maxit,
+                        double rel_tol, double *delta, int64_t ldd, int *its, void *stream) {
+    if (!M || k < 0 || k > 128 || maxit < 0 || !(rel_tol >= 0.0) || (k > 0 && (!R || !delta || ldr < k || ldd < k)))
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_pcg: invalid argument");
+    if (!A || !csr_ok(A) || A->n != M->amg.rows[0])
+        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_pcg: A does not match the hierarchy");
+    if (k == 0) return GCGE_OK;
+    try {
+        hipStream_t st = (hipStream_t)stream;
+        StepCtx &C = step_ctx();
+        std::lock_guard<std::mutex> lk(C.mu);
+        std::lock_guard<std::mutex> lk2(M->mu);
+        C.stg.st = st;
+        Operator op;
+        int rc = build_step_operator(A, GCGE_B_IDENTITY, nullptr, st, op);
+        if (rc) return rc;
+        const int64_t n = op.n;
+        const int64_t ld = round_up(k, 4);
+        Buffers bufs;
+        void *vecs = nullptr, *cm = nullptr;
+        double *m64 = nullptr;
+        hipError_t e = bufs.alloc((void **)&m64, sizeof(double) * std::max<int64_t>(op.nnz, 1));
+        if (e == hipSuccess) e = bufs.alloc(&vecs, sizeof(double) * 5 * n * ld);
+        if (e == hipSuccess) e = bufs.alloc(&cm, 8 * sizeof(double) * (ld + 16) + 64);
+        if (e == hipSuccess) e = op.shifted(0.0, m64, nullptr, st);
+        std::string err;
+        if (e == hipSuccess) {
+            const size_t slot = sizeof(double) * (ld + 16);
+            char *c8 = (char *)cm;
+            double *v = (double *)vecs;
+            CgState<double> cs{(double *)c8, (double *)(c8 + slot), (double *)(c8 + 2 * slot),
+                               (double *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
+                               (int *)(c8 + 6 * slot), (double *)(c8 + 7 * slot)};
+            CgRunner<double> runner{n, C.ws, st, nullptr, nullptr, err};
+            rc = runner.run_pcg(op.csr_of(m64), M->amg, R, ldr, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld,
+                                v + 3 * n * ld, v + 4 * n * ld, ld, cs, nullptr);
+            if (!rc) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
+            if (!rc && e == hipSuccess && its) e = C.stg.download(its, cs.its, sizeof(int) * k);
+        }
+        if (e == hipSuccess) e = C.stg.sync();
+        bufs.release();
+        op.destroy();
+        if (rc) return step_fail(rc, err);
+        if (e != hipSuccess) return step_hip(e, "gcge_pcg");
+        return GCGE_OK;
+    } catch (...) {
+        return step_fail(GCGE_ERR_INTERNAL, "gcge_pcg: internal error");
     }
 }
 

@@ -91,6 +91,14 @@ def test_invalid_arguments_return_codes_without_gpu(lib):
     assert lib.gcge_small_eigh(-1, None, None, None, 0) == _lib.GCGE_ERR_INVALID_ARG
     assert lib.gcge_spmm(None, None, 0, 0, None, 0, None) == _lib.GCGE_ERR_INVALID_ARG
     lib.gcge_destroy(None)
+    amg = ctypes.c_void_p()
+    assert lib.gcge_amg_create(None, 10, 512, None, ctypes.byref(amg)) == _lib.GCGE_ERR_INVALID_ARG
+    assert not amg.value
+    assert lib.gcge_amg_apply(None, None, 0, 1, None, 0, None) == _lib.GCGE_ERR_INVALID_ARG
+    nl = ctypes.c_int(0)
+    assert lib.gcge_amg_levels(None, ctypes.byref(nl), None, None, 0) == _lib.GCGE_ERR_INVALID_ARG
+    assert lib.gcge_pcg(None, None, None, 0, 1, 30, 1e-2, None, 0, None, None) == _lib.GCGE_ERR_INVALID_ARG
+    lib.gcge_amg_destroy(None)
 
 
 def test_product_path_does_not_import_the_oracle():

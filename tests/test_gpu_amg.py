@@ -1,0 +1,240 @@
+"""Parity of the STEP 6 preconditioner (algebraic multigrid V-cycle, PCG at
+theta = 0; Section 2's suggestion) with the CPU oracle, through the C ABI:
+hierarchy (level sizes, aggregates bit-exact), V-cycle output, PCG iterates,
+full-size properties at 128^3, and eigenvalues of the preconditioned solver."""
+import numpy as np
+import pytest
+
+import oracle.amg as oamg
+import oracle as orc
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_06552_amd as gg
+    gg._lib.load()
+    return gg
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "lap2d_24": lambda: wl.laplace2d_5pt(24),
+    "lap3d_12": lambda: wl.laplace3d_7pt(12),
+    "varcoef_10": lambda: wl.varcoef3d_7pt(10),
+    "q1fem_6": lambda: wl.q1_fem(6)[0],
+}
+
+
+@pytest.fixture(scope="module")
+def hier():
+    """Oracle hierarchies, computed once (coarse_max 40: three or more levels)."""
+    out = {}
+    for name, make in CASES.items():
+        A = make()
+        out[name] = (A, oamg.amg_setup(A, coarse_max=40, max_levels=10))
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_matches_oracle(g, hier, name):
+    A, H = hier[name]
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Amg(Ad, max_levels=10, coarse_max=40) as M:
+        lv = M.levels()
+        assert [r for r, _ in lv] == [L["n"] for L in H]
+        assert len(lv) >= 3
+        for l in range(len(H) - 1):
+            np.testing.assert_array_equal(M.aggregates(l), H[l]["agg"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k", [1, 7, 50])
+def test_vcycle_matches_oracle(g, hier, name, k):
+    A, H = hier[name]
+    rng = np.random.default_rng(100 + k)
+    B = rng.standard_normal((A.n, k))
+    ref = oamg.amg_vcycle(H, B)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Amg(Ad, max_levels=10, coarse_max=40) as M:
+        Y = host(M.apply(dev(B)))
+    err = np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() < 1e-12, err.max()
+
+
+def test_single_level_is_the_exact_inverse(g):
+    A = wl.laplace2d_5pt(10)
+    Ad = g.DeviceCsr.from_csr(A)
+    B = np.random.default_rng(5).standard_normal((A.n, 6))
+    with g.Amg(Ad, max_levels=10, coarse_max=200) as M:
+        assert len(M.levels()) == 1
+        Y = host(M.apply(dev(B)))
+    np.testing.assert_allclose(Y, np.linalg.solve(A.to_dense(), B), rtol=1e-11, atol=1e-13)
+
+
+def test_vcycle_on_strided_views_and_repeated_calls(g, hier):
+    A, H = hier["lap3d_12"]
+    Ad = g.DeviceCsr.from_csr(A)
+    rng = np.random.default_rng(9)
+    with g.Amg(Ad, max_levels=10, coarse_max=40) as M:
+        for k in (50, 13, 50):   # work vectors sized by the first call, reused
+            B = rng.standard_normal((A.n, k))
+            Bd = torch.zeros((A.n, k + 5), dtype=torch.float64, device="cuda")
+            Bd[:, :k] = dev(B)
+            Yd = torch.full((A.n, k + 3), 7.0, dtype=torch.float64, device="cuda")
+            M.apply(Bd[:, :k], Yd[:, :k])
+            Y = host(Yd)
+            ref = oamg.amg_vcycle(H, B)
+            assert np.abs(Y[:, :k] - ref).max() < 1e-12 * np.abs(ref).max()
+            assert np.all(Y[:, k:] == 7.0)
+
+
+@pytest.mark.parametrize("name", ["lap3d_12", "q1fem_6"])
+def test_pcg_matches_oracle(g, hier, name):
+    A, H = hier[name]
+    k = 9
+    R = np.random.default_rng(11).standard_normal((A.n, k))
+    X_ref, its_ref = oamg.pcg_columnwise(A, H, R, maxit=30, rel_tol=1e-6)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Amg(Ad, max_levels=10, coarse_max=40) as M:
+        D, its = g.pcg(Ad, M, dev(R), maxit=30, rel_tol=1e-6)
+    X = host(D)
+    np.testing.assert_array_equal(its, its_ref)
+    err = np.linalg.norm(X - X_ref, axis=0) / np.linalg.norm(X_ref, axis=0)
+    assert err.max() < 1e-9, err.max()
+
+
+def test_pcg_fixed_length_and_zero_column(g, hier):
+    A, H = hier["lap2d_24"]
+    R = np.random.default_rng(12).standard_normal((A.n, 4))
+    R[:, 2] = 0.0   # a zero right-hand side stays zero, zero iterations
+    X_ref, its_ref = oamg.pcg_columnwise(A, H, R, maxit=3, rel_tol=0.0)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Amg(Ad, max_levels=10, coarse_max=40) as M:
+        D, its = g.pcg(Ad, M, dev(R), maxit=3, rel_tol=0.0)
+    np.testing.assert_array_equal(its, its_ref)
+    assert its.tolist() == [3, 3, 0, 3]
+    X = host(D)
+    assert np.all(X[:, 2] == 0.0)
+    np.testing.assert_allclose(X, X_ref, rtol=1e-10, atol=1e-12 * np.abs(X_ref).max())
+
+
+def test_invalid_arguments(g):
+    A = wl.laplace2d_5pt(8)
+    Ad = g.DeviceCsr.from_csr(A)
+    with pytest.raises(g.GcgeError):
+        g.Amg(Ad, max_levels=0)
+    with pytest.raises(g.GcgeError):
+        g.Amg(Ad, coarse_max=5000)
+    bad = wl.laplace2d_5pt(8)
+    bad = bad.with_values(np.where(bad.row_of_entry() == bad.colind, -bad.val, bad.val))   # negative diagonal
+    with pytest.raises(g.GcgeError):
+        g.Amg(g.DeviceCsr.from_csr(bad))
+    with g.Amg(Ad, coarse_max=10) as M:
+        with pytest.raises(g.GcgeError):
+            M.apply(torch.zeros((A.n, 129), dtype=torch.float64, device="cuda"))
+        other = g.DeviceCsr.from_csr(wl.laplace2d_5pt(9))
+        with pytest.raises(g.GcgeError):
+            g.pcg(other, M, torch.zeros((81, 2), dtype=torch.float64, device="cuda"))
+
+
+# ------------------------------------------------------------ full size (128^3)
+
+@pytest.fixture(scope="module")
+def big(g):
+    A = wl.laplace3d_7pt(128)
+    Ad = g.DeviceCsr.from_csr(A)
+    M = g.Amg(Ad)
+    yield A, Ad, M
+    M.close()
+
+
+def test_fullsize_hierarchy_shape(big):
+    A, Ad, M = big
+    lv = M.levels()
+    print("levels", lv, flush=True)
+    rows = [r for r, _ in lv]
+    assert rows[0] == 128 ** 3 and rows[-1] <= 512
+    assert all(rows[i + 1] < rows[i] / 4 for i in range(len(rows) - 1))
+
+
+def test_fullsize_vcycle_symmetric_positive_and_sampled_rows(big):
+    A, Ad, M = big
+    n, k = A.n, 8
+    rng = np.random.default_rng(21)
+    U = rng.standard_normal((n, k))
+    V = rng.standard_normal((n, k))
+    VU = host(M.apply(dev(U)))
+    VV = host(M.apply(dev(V)))
+    lhs = np.einsum("ij,ij->j", U, VV)
+    rhs = np.einsum("ij,ij->j", VU, V)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11)
+    assert np.all(np.einsum("ij,ij->j", U, VU) > 0)
+    # the V-cycle is an approximate inverse: ||A V u - u|| / ||u|| well below 1
+    AVU = orc.spmm(A, VU)
+    red = np.linalg.norm(AVU - U, axis=0) / np.linalg.norm(U, axis=0)
+    print("||A V u - u|| / ||u||", red.max(), flush=True)
+    assert red.max() < 0.9
+
+
+def test_fullsize_pcg_reaches_tolerance(big):
+    A, Ad, M = big
+    k = 50
+    R = np.random.default_rng(22).standard_normal((A.n, k))
+    D, its = __import__("paper_2111_06552_amd").pcg(Ad, M, dev(R), maxit=30, rel_tol=1e-2)
+    X = host(D)
+    print("pcg iterations", its.min(), its.max(), flush=True)
+    assert its.max() < 15
+    res = np.linalg.norm(R - orc.spmm(A, X), axis=0) / np.linalg.norm(R, axis=0)
+    assert res.max() <= 1e-2 * (1 + 1e-6)
+
+
+# ------------------------------------------------------------ preconditioned solver
+
+def test_solver_with_multigrid_matches_closed_form(g):
+    A = wl.laplace2d_5pt(64)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, None, 10, 1e-8, block_size=10, precond=1, amg_coarse=64) as s:
+        lam, X, st = s.solve()
+    h = 1.0 / 65
+    sv = np.sin(np.arange(1, 65) * np.pi * h / 2) ** 2
+    ref = np.sort((4.0 / h ** 2 * (sv[:, None] + sv[None, :])).ravel())[:10]
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    assert st["max_rel_residual"] <= 1e-8
+
+
+@pytest.mark.parametrize("name,make,nev,bs", [
+    ("lap3d_10_diagB", lambda: (wl.laplace3d_7pt(10), "diag", wl.diag_uniform(1000)), 20, 5),
+    ("q1fem_9", lambda: (wl.q1_fem(9)[0], "csr", wl.q1_fem(9)[1]), 24, 6),
+])
+def test_solver_with_multigrid_matches_oracle(g, name, make, nev, bs):
+    A, bkind, B = make()
+    ref = orc.pencil_eigs(A, bkind, B, nev + 6)[0][:nev]
+    Ad = g.DeviceCsr.from_csr(A)
+    Bd = dev(B) if bkind == "diag" else (g.DeviceCsr.from_csr(B) if bkind == "csr" else None)
+    with g.Solver(Ad, Bd, nev, 1e-8, block_size=bs, precond=1, amg_coarse=64) as s:
+        lam, X, st = s.solve()
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    assert st["max_rel_residual"] <= 1e-8
+
+
+def test_solver_multigrid_rejects_mixed_precision(g):
+    A = wl.laplace2d_5pt(16)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, None, 4, 1e-8, block_size=4, precond=1, precision=1) as s:
+        with pytest.raises(g.GcgeError):
+            s.solve()
