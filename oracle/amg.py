@@ -23,9 +23,10 @@ the choices below, so that both sides compute the same preconditioner:
   omega_l = 4 / (3 rho_l);
 * smoothed prolongator P = (I - omega_l D^-1 A) P_t, restriction R = P^T,
   Galerkin coarse operator A_{l+1} = R A P;
-* coarsening stops when a level has at most ``coarse_max`` rows, when
-  ``max_levels`` levels exist, or when a level does not shrink; the last
-  level is solved exactly (Cholesky);
+* a level is the last one when it has at most ``coarse_max`` rows, when
+  ``max_levels`` levels exist, when it stores more than ``MAX_ROW_FILL``
+  (400) entries per row, or when aggregation would keep more than half of its
+  rows; the last level is solved exactly (Cholesky);
 * symmetric V-cycle: one damped-Jacobi sweep (weight omega_l D^-1) before
   and after the coarse correction, starting from zero.
 
@@ -44,6 +45,7 @@ from .core import cholesky, solve_lower, solve_lower_t, spmm
 
 STRENGTH_EPS0 = 0.08
 TIE_REL = 1e-8
+MAX_ROW_FILL = 400
 
 
 class SparseRows:
@@ -189,10 +191,10 @@ def amg_setup(A, coarse_max=512, max_levels=10):
         if np.any(d <= 0):
             raise ValueError("AMG needs a positive diagonal")
         L = {"A": cur, "Ad": Ad, "dinv": 1.0 / d, "n": cur.n}
-        last = cur.n <= coarse_max or lev == max_levels - 1
+        last = cur.n <= coarse_max or lev == max_levels - 1 or cur.nnz > MAX_ROW_FILL * cur.n
         if not last:
             agg, nagg = aggregate(cur, STRENGTH_EPS0 * 0.5 ** lev)
-            if nagg >= cur.n:
+            if 2 * nagg > cur.n:
                 last = True
         if last:
             L["L"] = cholesky(Ad)

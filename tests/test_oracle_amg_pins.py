@@ -125,3 +125,21 @@ def test_pcg_solves_and_beats_plain_cg():
     np.testing.assert_allclose(X, np.linalg.solve(A.to_dense(), R), rtol=1e-7, atol=1e-9 * np.abs(X).max())
     _, its_cg = cg_columnwise(A, "identity", None, 0.0, R, maxit=500, rel_tol=1e-10)
     assert its.max() * 3 < its_cg.min(), (its, its_cg)
+
+
+def test_coarsening_stops_on_poor_aggregation_and_dense_levels():
+    # No off-diagonal entries: every row is a singleton aggregate, so
+    # aggregation would keep all rows and the first level is the coarsest.
+    n = 50
+    D = amg._from_dense(np.diag(np.arange(1.0, n + 1)))
+    H = amg.amg_setup(D, coarse_max=4)
+    assert len(H) == 1
+    # A level storing more than 400 entries per row is not coarsened.
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((450, 450))
+    M = amg._from_dense(G @ G.T / 450 + np.eye(450))
+    assert M.nnz > 400 * M.n
+    assert len(amg.amg_setup(M, coarse_max=4)) == 1
+    b = rng.standard_normal((450, 2))
+    np.testing.assert_allclose(amg.amg_vcycle(amg.amg_setup(M, coarse_max=4), b),
+                               np.linalg.solve(M.to_dense(), b), rtol=1e-10)
