@@ -81,6 +81,10 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": per_launch,
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "avg_launch_ms_all_widths": p["ms"] / p["launches"], "launches_all_widths": p["launches"]}
+    if name == "amg_vcycle":   # several kernels per application: time only
+        return {"kernel": "multigrid V-cycle (all levels, one application)", "bound": None,
+                "avg_launch_ms": p["ms"] / p["launches"], "launches": p["launches"],
+                "columns_per_launch": p["columns"] / p["launches"]}
     kern = {"rotation_gemm": "k_gemm (Ritz rotation V_u xhat)", "p_gemm": "k_gemm (P block V_u phat)",
             "gram": "k_gram_lds + k_tile_reduce (Gram products)"}[name]
     per_launch = 2.0 * n * k
@@ -224,6 +228,9 @@ def main():
                     help="inner CG stop at this relative residual (0: always cg-max-iter iterations)")
     ap.add_argument("--shift", type=int, choices=(0, 1), default=1,
                     help="1: inner CG on A - theta B with theta the largest converged eigenvalue; 0: theta = 0")
+    ap.add_argument("--precond", type=int, choices=(0, 1), default=0,
+                    help="1: STEP 6 as CG preconditioned by the algebraic multigrid V-cycle at theta = 0 "
+                         "(FP64 only; the mixed run is skipped)")
     ap.add_argument("--orth", type=int, choices=(2, 3), default=3,
                     help="STEP 2 orthogonalization: 3 RecursiveOrthSVD (default), 2 modified block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,7 +278,8 @@ def main():
 
     def run(prec, steps, warmup):
         opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1, orth=args.orth,
-                    cg_max_iter=args.cg_max_iter, cg_rel_tol=args.cg_rel_tol, shift=args.shift)
+                    cg_max_iter=args.cg_max_iter, cg_rel_tol=args.cg_rel_tol, shift=args.shift,
+                    precond=args.precond)
         with g.Solver(Ad, Bd, nev, tol, **opts) as s:
             for i in range(warmup):
                 lam, _, st = s.solve(evecs)
@@ -297,7 +305,8 @@ def main():
         "config": {"workload": args.workload, "grid": p["grid"], "n": A.n, "nnz": A.nnz, "nev": nev,
                    "block_size": bs, "tol": tol, "B": bkind, "moving": bool(p["moving"]),
                    "orthogonalization": "Algorithm 3" if args.orth == 3 else "Algorithm 2",
-                   "cg_max_iter": args.cg_max_iter, "cg_rel_tol": args.cg_rel_tol, "shift": bool(args.shift)},
+                   "cg_max_iter": args.cg_max_iter, "cg_rel_tol": args.cg_rel_tol, "shift": bool(args.shift),
+                   "inner_preconditioner": "algebraic multigrid V-cycle (theta = 0)" if args.precond else None},
     }
     st = s64[-1]
     out["solve"] = {k: st[k] for k in ("iterations", "nconv", "moves", "cg_iterations", "spmm_columns",
@@ -312,7 +321,7 @@ def main():
     out["roofline"] = roof
     out["kernel_rooflines"] = {c: class_roofline(c, prof[c], A.n, A.nnz, bs=bs) for c in prof}
     out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"] / args.steps, 2) for c in prof}
-    if not args.no_mixed:
+    if not args.no_mixed and not args.precond:
         tm, sm, lamm = run("mixed", args.steps, args.warmup)
         out["mixed"] = {"value": float(tm.mean()), "unit": "s", "ms_per_step": float(tm.mean() * 1e3),
                         "speedup_vs_fp64": float(t64.mean() / tm.mean()),

@@ -13,9 +13,13 @@
 //                 by a relative 1e-8, so rounding cannot change the choice);
 //   prolongator   P = (I - omega D^-1 A) P_t, P_t[i, agg(i)] = |agg(i)|^-1/2,
 //                 omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / a_ii;
-//   coarse level  R = P^T, A_next = R A P; the last level (at most coarse_max
-//                 rows, or the level limit, or no coarsening) is inverted
-//                 densely (Cholesky) and applied as a GEMM;
+//   coarse level  R = P^T, A_next = R A P; a level is the last one when it has
+//                 at most coarse_max rows, at the level limit, when it stores
+//                 more than 400 entries per row (Galerkin products of denser
+//                 levels cost more than they save), or when aggregation would
+//                 keep more than half of its rows; the last level is inverted
+//                 densely (Cholesky, at most 4096 rows, else the setup fails)
+//                 and applied as a GEMM;
 //   V-cycle       x = w b (one damped Jacobi sweep from zero, w = omega D^-1),
 //                 t = b - A x, x += P V(R t), y = x + w (b - A x): symmetric
 //                 and positive definite, so it preconditions CG.
@@ -344,17 +348,19 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
         } else {
             e = upload_csr(owned, cur, L.A);
         }
-        bool last = cur.n <= coarse_max || lev == max_levels - 1;
+        bool last = cur.n <= coarse_max || lev == max_levels - 1 || cur.nnz() > AMG_MAX_ROW_FILL * cur.n;
         std::vector<int32_t> ag;
         int64_t nagg = 0;
         if (!last) {
             aggregate(cur, d, STRENGTH_EPS0 * std::ldexp(1.0, -lev), ag, nagg);
-            if (nagg >= cur.n) last = true;
+            if (2 * nagg > cur.n) last = true;
         }
         if (last) {
             if (cur.n > AMG_COARSE_LIMIT) {
-                err = "amg: coarsest level has " + std::to_string(cur.n) + " rows (limit " +
-                      std::to_string(AMG_COARSE_LIMIT) + "); raise the level limit";
+                err = "amg: coarsening stops at level " + std::to_string(lev) + " with " + std::to_string(cur.n) +
+                      " rows and " + std::to_string(cur.nnz() / cur.n) + " entries per row, above the " +
+                      std::to_string(AMG_COARSE_LIMIT) + " rows of a dense coarsest level: this operator is not "
+                      "suited to the aggregation multigrid";
                 release();
                 return GCGE_ERR_INVALID_ARG;
             }
@@ -400,7 +406,7 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
 }
 
 int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
-               hipStream_t st, std::string &err) {
+               hipStream_t st, std::string &err, const int *skip) {
     if (lv.empty()) {
         err = "amg: no hierarchy";
         return GCGE_ERR_INVALID_ARG;
@@ -462,10 +468,13 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
         Affine<double> res;
         res.b = bl;
         res.ldb = ldbl;
-        if (e == hipSuccess) e = spmm_affine<double>(V.A, X[l], ldw, k, T[l], ldw, res, st);
+        if (e == hipSuccess) e = spmm_affine<double>(V.A, X[l], ldw, k, T[l], ldw, res, st, nullptr, 0, nullptr,
+                                                     nullptr, skip);
+        Affine<double> restrict_;   // b_next = R t  (0 - (-1) R t)
+        restrict_.ws = -1.0;
         if (e == hipSuccess)
-            e = spmm<double>(V.R, nullptr, nullptr, nullptr, 0, 0, T[l], ldw, k, Bv[l + 1], ldw, nullptr, 0,
-                             nullptr, nullptr, st);
+            e = spmm_affine<double>(V.R, T[l], ldw, k, Bv[l + 1], ldw, restrict_, st, nullptr, 0, nullptr, nullptr,
+                                    skip);
         bl = Bv[l + 1];
         ldbl = ldw;
     }
@@ -488,7 +497,7 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
         cor.z = X[l];
         cor.ldz = ldw;
         cor.ws = -1.0;
-        e = spmm_affine<double>(V.P, Y[l + 1], ldw, k, X[l], ldw, cor, st);
+        e = spmm_affine<double>(V.P, Y[l + 1], ldw, k, X[l], ldw, cor, st, nullptr, 0, nullptr, nullptr, skip);
         Affine<double> sm;
         sm.b = bb;
         sm.ldb = ldbb;
@@ -500,9 +509,9 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
         const int64_t ldo = l == 0 ? ldy : ldw;
         if (e == hipSuccess) {
             if (l == 0 && part != nullptr)
-                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, b, ldb, part, nparts);
+                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, b, ldb, part, nparts, skip);
             else
-                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st);
+                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, nullptr, 0, nullptr, nullptr, skip);
         }
     }
     if (e != hipSuccess) {

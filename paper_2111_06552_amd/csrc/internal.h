@@ -99,10 +99,11 @@ struct Affine {
 };
 // With zdot != nullptr the SpMM also writes partials of the column dots
 // y . zdot (part[c * np + g], np in *nparts), as the RED = 2 products do.
+// With skip != nullptr the kernel does nothing when skip[0] == 0 (device flag).
 template <typename T>
 hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const Affine<T> &af,
                        hipStream_t st, const T *zdot = nullptr, int64_t ldzdot = 0, T *part = nullptr,
-                       int *nparts = nullptr);
+                       int *nparts = nullptr, const int *skip = nullptr);
 
 template <typename T>
 hipError_t spmm(const DevCsr<T> &A, const T *vb, const T *dg, const T *sigma, int mode, int red,
@@ -231,13 +232,16 @@ struct Amg {
     // rows when ldb, ldy are even).  With part != nullptr the last kernel also
     // writes per-work-group partials of the column dots b . y (part[c * np + g],
     // np in *nparts).
+    // With skip != nullptr every SpMM of the cycle is skipped on the device
+    // when skip[0] == 0 (the CG's count of active columns).
     int apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
-              hipStream_t st, std::string &err);
+              hipStream_t st, std::string &err, const int *skip = nullptr);
     void release();
     ~Amg() { release(); }
 };
 constexpr int AMG_MAX_LEVELS = 16;
 constexpr int64_t AMG_COARSE_LIMIT = 4096;   // largest coarsest level (dense inverse)
+constexpr int64_t AMG_MAX_ROW_FILL = 400;    // a level denser than this is not coarsened further
 
 // ------------------------------------------------------------- host dense
 // Symmetric eigensolver: a (n x n, row-major, destroyed), w ascending, z (n x

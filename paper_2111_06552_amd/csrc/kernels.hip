@@ -533,21 +533,21 @@ template hipError_t cg_spmm<float>(const DevCsr<float> &, const float *, float *
 
 template <typename T>
 hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y, int64_t ldy, const Affine<T> &af,
-                       hipStream_t st, const T *zdot, int64_t ldzdot, T *part, int *nparts) {
+                       hipStream_t st, const T *zdot, int64_t ldzdot, T *part, int *nparts, const int *skip) {
     if (nparts) *nparts = 0;
     if (A.n == 0 || k == 0) return hipSuccess;
     if (k > 128) return hipErrorInvalidValue;
     if (zdot != nullptr) {
         if (part == nullptr || nparts == nullptr) return hipErrorInvalidValue;
         return spmm_dispatch<T, 3, 2>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, zdot, ldzdot, part, nparts,
-                                      nullptr, st, af);
+                                      skip, st, af);
     }
     return spmm_dispatch<T, 3, 0>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, nullptr, 0, nullptr, nullptr,
-                                  nullptr, st, af);
+                                  skip, st, af);
 }
 template hipError_t spmm_affine<double>(const DevCsr<double> &, const double *, int64_t, int, double *, int64_t,
                                         const Affine<double> &, hipStream_t, const double *, int64_t, double *,
-                                        int *);
+                                        int *, const int *);
 
 // ---------------------------------------------------------------------------
 // fixed-order column sums of partials (one work-group, 16 waves)

@@ -195,7 +195,7 @@ struct CgRunner {
             if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
             if (e != hipSuccess) return fail(e, "pcg iteration");
             pb = prof ? prof->begin(st) : -1;
-            rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err);
+            rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err, cs.flags);
             if (prof) prof->end(6, pb, k, st);
             if (rc) return rc;
             e = pcg_rz<T>(part, nparts, k, false, cs, st);
@@ -203,20 +203,25 @@ struct CgRunner {
             if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, z, ld, cs, st);
             if (prof) prof->end(2, pb, k, st);
             if (e != hipSuccess) return fail(e, "pcg iteration");
-            if (pinned_flag != nullptr && (it % 2) == 1) {
-                if (pending && hipEventQuery(ev) == hipSuccess) {
+            // A preconditioned iteration is long and few are needed: after
+            // queuing an iteration, wait for the count of active columns copied
+            // after the previous one, so the host stays one iteration ahead and
+            // stops right after the last column converges (an iteration queued
+            // past that point skips its SpMMs and updates on the device).
+            if (pinned_flag != nullptr) {
+                if (pending) {
+                    e = hipEventSynchronize(ev);
+                    if (e != hipSuccess) return fail(e, "pcg poll");
                     pending = false;
                     if (*pinned_flag == 0) {
                         ++it;
                         break;
                     }
                 }
-                if (!pending) {
-                    e = hipMemcpyAsync(pinned_flag, cs.flags, sizeof(int), hipMemcpyDeviceToHost, st);
-                    if (e == hipSuccess) e = hipEventRecord(ev, st);
-                    if (e != hipSuccess) return fail(e, "pcg poll");
-                    pending = true;
-                }
+                e = hipMemcpyAsync(pinned_flag, cs.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipEventRecord(ev, st);
+                if (e != hipSuccess) return fail(e, "pcg poll");
+                pending = true;
             }
         }
         if (total_its) *total_its += it;

@@ -203,6 +203,21 @@ def test_fullsize_pcg_reaches_tolerance(big):
     assert res.max() <= 1e-2 * (1 + 1e-6)
 
 
+def test_high_contrast_fem_is_rejected_in_bounded_time(g):
+    # Q1 FEM with log-uniform coefficients over two decades: aggregation by the
+    # strength threshold coarsens slowly and the smoothed Galerkin levels fill
+    # in (about 900 entries per row at level 2), so coarsening stops above the
+    # dense coarsest-level limit and the setup reports it.
+    import time
+    A = wl.q1_fem(96)[0]
+    Ad = g.DeviceCsr.from_csr(A)
+    t = time.time()
+    with pytest.raises(g.GcgeError, match="not suited"):
+        g.Amg(Ad)
+    print("setup until the error", round(time.time() - t, 2), "s", flush=True)
+    assert time.time() - t < 60
+
+
 # ------------------------------------------------------------ preconditioned solver
 
 def test_solver_with_multigrid_matches_closed_form(g):
