@@ -134,10 +134,12 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *                         (gcge_small_eigh)
  *  "precond"      [0]     1: STEP 6 runs preconditioned CG with the algebraic multigrid
  *                         V-cycle of A (gcge_amg_create) and theta = 0, as Section 2
- *                         suggests for discretized PDE operators; needs precision FP64
- *                         (INVALID_ARG at gcge_solve otherwise).  The hierarchy is built
+ *                         suggests for discretized PDE operators.  With precision MIXED
+ *                         the PCG and the V-cycle run in FP32 (FP32 copies of the
+ *                         levels; the coarsest solve stays FP64).  The hierarchy is built
  *                         at the first STEP 6 (its time counts in time_ms[5]) and again
- *                         after gcge_update_values.
+ *                         after gcge_update_values; a setup failure (e.g. an operator the
+ *                         aggregation cannot coarsen) is returned by gcge_solve.
  *  "amg_levels"   [10]    level limit of that hierarchy (1 .. 16)
  *  "amg_coarse"   [512]   rows at or below which a level is the coarsest (1 .. 4096)
  * Unknown keys or out-of-range values return INVALID_ARG. */

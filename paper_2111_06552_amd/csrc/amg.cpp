@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -289,6 +290,20 @@ hipError_t upload_csr(std::vector<void *> &owned, const HCsr &H, DevCsr<double> 
     return e;
 }
 
+// FP32 copy of the values of an uploaded level matrix (same index arrays).
+hipError_t upload_f32(std::vector<void *> &owned, const HCsr &H, const DevCsr<double> &D, DevCsr<float> &F) {
+    std::vector<float> v(H.va.begin(), H.va.end());
+    void *p = nullptr;
+    hipError_t e = upload(owned, &p, v.data(), sizeof(float) * v.size());
+    F.n = D.n;
+    F.nnz = D.nnz;
+    F.rowptr = D.rowptr;
+    F.colind = D.colind;
+    F.val = (const float *)p;
+    F.uorder = nullptr;
+    return e;
+}
+
 inline size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
@@ -347,6 +362,7 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
             L.A = A0;
         } else {
             e = upload_csr(owned, cur, L.A);
+            if (e == hipSuccess) e = upload_f32(owned, cur, L.A, L.A32);
         }
         bool last = cur.n <= coarse_max || lev == max_levels - 1 || cur.nnz() > AMG_MAX_ROW_FILL * cur.n;
         std::vector<int32_t> ag;
@@ -380,9 +396,12 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
         const double om = 4.0 / (3.0 * r);
         std::vector<double> w(cur.n);
         for (int64_t i = 0; i < cur.n; ++i) w[i] = om / d[i];
-        void *pw = nullptr;
+        std::vector<float> w32(w.begin(), w.end());
+        void *pw = nullptr, *pw32 = nullptr;
         if (e == hipSuccess) e = upload(owned, &pw, w.data(), sizeof(double) * w.size());
+        if (e == hipSuccess) e = upload(owned, &pw32, w32.data(), sizeof(float) * w32.size());
         L.w = (double *)pw;
+        L.w32 = (float *)pw32;
         HCsr P, R, AP, Ac;
         smoothed_p(cur, d, ag, nagg, om, P);
         transpose(P, R);
@@ -390,6 +409,8 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
         spgemm(R, AP, Ac);
         if (e == hipSuccess) e = upload_csr(owned, P, L.P);
         if (e == hipSuccess) e = upload_csr(owned, R, L.R);
+        if (e == hipSuccess) e = upload_f32(owned, P, L.P, L.P32);
+        if (e == hipSuccess) e = upload_f32(owned, R, L.R, L.R32);
         if (e != hipSuccess) break;
         agg.push_back(std::move(ag));
         omega.push_back(om);
@@ -405,8 +426,10 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
     return GCGE_OK;
 }
 
-int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
-               hipStream_t st, std::string &err, const int *skip) {
+template <typename T>
+int Amg::apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *nparts, hipStream_t st,
+               std::string &err, const int *skip) {
+    constexpr bool F32 = std::is_same<T, float>::value;
     if (lv.empty()) {
         err = "amg: no hierarchy";
         return GCGE_ERR_INVALID_ARG;
@@ -415,18 +438,24 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
         err = "amg: invalid apply arguments";
         return GCGE_ERR_INVALID_ARG;
     }
+    if (F32 && lv.size() > 1 && lv[0].A32.val == nullptr) {
+        err = "amg: no FP32 level-0 operator";
+        return GCGE_ERR_INVALID_ARG;
+    }
     if (nparts) *nparts = 0;
     if (k == 0) return GCGE_OK;
     hipError_t e = hipSuccess;
     const int L = (int)lv.size() - 1;
+    const int64_t ldk = (k + 3) / 4 * 4;   // 16-byte rows for FP64 and FP32
     if (k > kcap) {
-        // x, t on every smoothed level; b, y on every level but the finest
-        const int64_t ld = (k + 1) / 2 * 2;
+        // x, t on every smoothed level, b, y on every level but the finest
+        // (sized for FP64), and two FP64 blocks for the coarsest solve
         size_t bytes = 0;
         for (int l = 0; l <= L; ++l) {
-            const size_t v = pad256(sizeof(double) * lv[l].n * ld);
+            const size_t v = pad256(sizeof(double) * lv[l].n * ldk);
             bytes += (l < L ? 2 * v : 0) + (l > 0 ? 2 * v : 0);
         }
+        bytes += 2 * pad256(sizeof(double) * lv[L].n * ldk);
         if (work) (void)hipFree(work);
         work = nullptr;
         work_bytes = 0;
@@ -439,79 +468,97 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
         }
         work_bytes = bytes;
         kcap = k;
-        ldw = ld;
+        ldw = ldk;
     }
-    // carve the work area (same layout for every k <= kcap)
-    std::vector<double *> X(L + 1, nullptr), T(L + 1, nullptr), Bv(L + 1, nullptr), Y(L + 1, nullptr);
+    std::vector<T *> X(L + 1, nullptr), Tv(L + 1, nullptr), Bv(L + 1, nullptr), Y(L + 1, nullptr);
+    double *c64a = nullptr, *c64b = nullptr;
     {
         char *p = (char *)work;
         for (int l = 0; l <= L; ++l) {
             const size_t v = pad256(sizeof(double) * lv[l].n * ldw);
             if (l < L) {
-                X[l] = (double *)p;
-                T[l] = (double *)(p + v);
+                X[l] = (T *)p;
+                Tv[l] = (T *)(p + v);
                 p += 2 * v;
             }
             if (l > 0) {
-                Bv[l] = (double *)p;
-                Y[l] = (double *)(p + v);
+                Bv[l] = (T *)p;
+                Y[l] = (T *)(p + v);
                 p += 2 * v;
             }
         }
+        c64a = (double *)p;
+        c64b = (double *)(p + pad256(sizeof(double) * lv[L].n * ldw));
     }
+    auto A_of = [&](int l) -> DevCsr<T> {
+        if constexpr (F32) return lv[l].A32; else return lv[l].A;
+    };
+    auto P_of = [&](int l) -> DevCsr<T> {
+        if constexpr (F32) return lv[l].P32; else return lv[l].P;
+    };
+    auto R_of = [&](int l) -> DevCsr<T> {
+        if constexpr (F32) return lv[l].R32; else return lv[l].R;
+    };
+    auto w_of = [&](int l) -> const T * {
+        if constexpr (F32) return lv[l].w32; else return lv[l].w;
+    };
     // descend: pre-smoothing, residual, restriction
-    const double *bl = b;
+    const T *bl = b;
     int64_t ldbl = ldb;
     for (int l = 0; l < L && e == hipSuccess; ++l) {
-        const AmgLevel &V = lv[l];
-        e = scale_rows(V.n, k, V.w, bl, ldbl, X[l], ldw, st);
-        Affine<double> res;
+        e = scale_rows<T>(lv[l].n, k, w_of(l), bl, ldbl, X[l], ldw, st);
+        Affine<T> res;
         res.b = bl;
         res.ldb = ldbl;
-        if (e == hipSuccess) e = spmm_affine<double>(V.A, X[l], ldw, k, T[l], ldw, res, st, nullptr, 0, nullptr,
-                                                     nullptr, skip);
-        Affine<double> restrict_;   // b_next = R t  (0 - (-1) R t)
-        restrict_.ws = -1.0;
         if (e == hipSuccess)
-            e = spmm_affine<double>(V.R, T[l], ldw, k, Bv[l + 1], ldw, restrict_, st, nullptr, 0, nullptr, nullptr,
-                                    skip);
+            e = spmm_affine<T>(A_of(l), X[l], ldw, k, Tv[l], ldw, res, st, nullptr, 0, nullptr, nullptr, skip);
+        Affine<T> restrict_;   // b_next = R t  (0 - (-1) R t)
+        restrict_.ws = T(-1);
+        if (e == hipSuccess)
+            e = spmm_affine<T>(R_of(l), Tv[l], ldw, k, Bv[l + 1], ldw, restrict_, st, nullptr, 0, nullptr, nullptr,
+                               skip);
         bl = Bv[l + 1];
         ldbl = ldw;
     }
-    // coarsest level: y_L = A_L^-1 b_L
+    // coarsest level: y_L = A_L^-1 b_L (dense inverse, FP64 GEMM)
     if (e == hipSuccess) {
         const int64_t nc = lv[L].n;
-        double *yL = L == 0 ? y : Y[L];
+        T *yL = L == 0 ? y : Y[L];
         const int64_t ldyL = L == 0 ? ldy : ldw;
         Segs S;
         S.add(cinv, nc, (int)nc);
-        e = gemm(nc, S, bl, ldbl, k, 1.0, 0.0, yL, ldyL, st);
-        if (L == 0 && part != nullptr && e == hipSuccess) e = coldot_part(nc, k, y, ldy, b, ldb, part, nparts, st);
+        if constexpr (F32) {
+            e = copy_cols<float, double>(nc, k, bl, ldbl, c64a, ldw, nullptr, st);
+            if (e == hipSuccess) e = gemm(nc, S, c64a, ldw, k, 1.0, 0.0, c64b, ldw, st);
+            if (e == hipSuccess) e = copy_cols<double, float>(nc, k, c64b, ldw, yL, ldyL, nullptr, st);
+        } else {
+            e = gemm(nc, S, bl, ldbl, k, 1.0, 0.0, yL, ldyL, st);
+        }
+        if (L == 0 && part != nullptr && e == hipSuccess) e = coldot_part<T>(nc, k, y, ldy, b, ldb, part, nparts, st);
     }
     // ascend: coarse correction, post-smoothing
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
-        const AmgLevel &V = lv[l];
-        const double *bb = l == 0 ? b : Bv[l];
+        const T *bb = l == 0 ? b : Bv[l];
         const int64_t ldbb = l == 0 ? ldb : ldw;
-        Affine<double> cor;
+        Affine<T> cor;
         cor.z = X[l];
         cor.ldz = ldw;
-        cor.ws = -1.0;
-        e = spmm_affine<double>(V.P, Y[l + 1], ldw, k, X[l], ldw, cor, st, nullptr, 0, nullptr, nullptr, skip);
-        Affine<double> sm;
+        cor.ws = T(-1);
+        e = spmm_affine<T>(P_of(l), Y[l + 1], ldw, k, X[l], ldw, cor, st, nullptr, 0, nullptr, nullptr, skip);
+        Affine<T> sm;
         sm.b = bb;
         sm.ldb = ldbb;
         sm.z = X[l];
         sm.ldz = ldw;
-        sm.w = V.w;
-        sm.ws = 1.0;
-        double *out = l == 0 ? y : Y[l];
+        sm.w = w_of(l);
+        sm.ws = T(1);
+        T *out = l == 0 ? y : Y[l];
         const int64_t ldo = l == 0 ? ldy : ldw;
         if (e == hipSuccess) {
             if (l == 0 && part != nullptr)
-                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, b, ldb, part, nparts, skip);
+                e = spmm_affine<T>(A_of(l), X[l], ldw, k, out, ldo, sm, st, b, ldb, part, nparts, skip);
             else
-                e = spmm_affine<double>(V.A, X[l], ldw, k, out, ldo, sm, st, nullptr, 0, nullptr, nullptr, skip);
+                e = spmm_affine<T>(A_of(l), X[l], ldw, k, out, ldo, sm, st, nullptr, 0, nullptr, nullptr, skip);
         }
     }
     if (e != hipSuccess) {
@@ -520,5 +567,9 @@ int Amg::apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, doub
     }
     return GCGE_OK;
 }
+template int Amg::apply<double>(const double *, int64_t, int, double *, int64_t, double *, int *, hipStream_t,
+                                std::string &, const int *);
+template int Amg::apply<float>(const float *, int64_t, int, float *, int64_t, float *, int *, hipStream_t,
+                               std::string &, const int *);
 
 }  // namespace gcge

@@ -137,15 +137,16 @@ hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> 
 template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st);
 // Y = diag(d) X (n x k row-major).
-hipError_t scale_rows(int64_t n, int k, const double *d, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                      hipStream_t st);
+template <typename T>
+hipError_t scale_rows(int64_t n, int k, const T *d, const T *X, int64_t ldx, T *Y, int64_t ldy, hipStream_t st);
 // Preconditioned CG: rz[c] = sum of the partials (init: beta = 0), or, for the
 // columns updated this iteration, beta = rz_new / rz and rz = rz_new.
 template <typename T>
 hipError_t pcg_rz(const T *part, int nparts, int k, bool init, CgState<T> cs, hipStream_t st);
 // Partials of the column dots x[:, c] . y[:, c] (part[c * np + g], np in *nparts).
-hipError_t coldot_part(int64_t n, int k, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
-                       int *nparts, hipStream_t st);
+template <typename T>
+hipError_t coldot_part(int64_t n, int k, const T *X, int64_t ldx, const T *Y, int64_t ldy, T *part, int *nparts,
+                       hipStream_t st);
 // SpMM of the CG iteration (q = M p with partial p.q), skipped when flags[0] == 0.
 template <typename T>
 hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int *nparts,
@@ -214,6 +215,8 @@ struct AmgLevel {
     int64_t n = 0;
     DevCsr<double> A, P, R;   // level operator, prolongator (n x n_next), restriction P^T
     double *w = nullptr;      // omega / a_ii of the damped Jacobi sweep
+    DevCsr<float> A32, P32, R32;   // FP32 copies for the V-cycle of the mixed-precision inner solve
+    float *w32 = nullptr;
 };
 struct Amg {
     std::vector<AmgLevel> lv;                 // the last level is solved with cinv
@@ -234,8 +237,12 @@ struct Amg {
     // np in *nparts).
     // With skip != nullptr every SpMM of the cycle is skipped on the device
     // when skip[0] == 0 (the CG's count of active columns).
-    int apply(const double *b, int64_t ldb, int k, double *y, int64_t ldy, double *part, int *nparts,
-              hipStream_t st, std::string &err, const int *skip = nullptr);
+    // T = float runs the cycle on the FP32 copies (the coarsest solve in FP64);
+    // it needs the FP32 level-0 operator from set_level0_f32.
+    template <typename T>
+    int apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *nparts, hipStream_t st,
+              std::string &err, const int *skip = nullptr);
+    void set_level0_f32(const DevCsr<float> &A32) { if (!lv.empty()) lv[0].A32 = A32; }
     void release();
     ~Amg() { release(); }
 };

@@ -548,6 +548,9 @@ hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y,
 template hipError_t spmm_affine<double>(const DevCsr<double> &, const double *, int64_t, int, double *, int64_t,
                                         const Affine<double> &, hipStream_t, const double *, int64_t, double *,
                                         int *, const int *);
+template hipError_t spmm_affine<float>(const DevCsr<float> &, const float *, int64_t, int, float *, int64_t,
+                                       const Affine<float> &, hipStream_t, const float *, int64_t, float *, int *,
+                                       const int *);
 
 // ---------------------------------------------------------------------------
 // fixed-order column sums of partials (one work-group, 16 waves)
@@ -959,22 +962,22 @@ __global__ __launch_bounds__(1024) void k_pcg_rz(const T *__restrict__ part, int
 
 // Column-dot partials: 64 lanes per row (two columns each), 4 rows per
 // work-group step; the four row groups are summed in LDS in a fixed order.
-__global__ __launch_bounds__(256) void k_coldot_part(int64_t n, int k, const double *__restrict__ X, int64_t ldx,
-                                                     const double *__restrict__ Y, int64_t ldy,
-                                                     double *__restrict__ part) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_coldot_part(int64_t n, int k, const T *__restrict__ X, int64_t ldx,
+                                                     const T *__restrict__ Y, int64_t ldy, T *__restrict__ part) {
     const int tid = threadIdx.x, grp = tid / 64, lane = tid % 64;
-    double s0 = 0.0, s1 = 0.0;
+    T s0 = T(0), s1 = T(0);
     const int c0 = lane, c1 = lane + 64;
     for (int64_t r = (int64_t)blockIdx.x * 4 + grp; r < n; r += (int64_t)gridDim.x * 4) {
         if (c0 < k) s0 = fma(X[r * ldx + c0], Y[r * ldy + c0], s0);
         if (c1 < k) s1 = fma(X[r * ldx + c1], Y[r * ldy + c1], s1);
     }
-    __shared__ double sh[4][128];
+    __shared__ T sh[4][128];
     sh[grp][c0] = s0;
     sh[grp][c1] = s1;
     __syncthreads();
     if (tid < 128 && tid < k) {
-        const double v = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
+        const T v = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
         part[(size_t)tid * gridDim.x + blockIdx.x] = v;
     }
 }
@@ -1092,15 +1095,21 @@ hipError_t pcg_rz(const T *part, int nparts, int k, bool init, CgState<T> cs, hi
     return hipGetLastError();
 }
 template hipError_t pcg_rz<double>(const double *, int, int, bool, CgState<double>, hipStream_t);
+template hipError_t pcg_rz<float>(const float *, int, int, bool, CgState<float>, hipStream_t);
 
-hipError_t coldot_part(int64_t n, int k, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
-                       int *nparts, hipStream_t st) {
+template <typename T>
+hipError_t coldot_part(int64_t n, int k, const T *X, int64_t ldx, const T *Y, int64_t ldy, T *part, int *nparts,
+                       hipStream_t st) {
     if (k < 1 || k > 128 || n < 1) return hipErrorInvalidValue;
     const int g = (int)std::min<int64_t>((n + 3) / 4, (int64_t)max_row_parts());
-    hipLaunchKernelGGL(k_coldot_part, dim3(g), dim3(256), 0, st, n, k, X, ldx, Y, ldy, part);
+    hipLaunchKernelGGL(k_coldot_part<T>, dim3(g), dim3(256), 0, st, n, k, X, ldx, Y, ldy, part);
     *nparts = g;
     return hipGetLastError();
 }
+template hipError_t coldot_part<double>(int64_t, int, const double *, int64_t, const double *, int64_t, double *,
+                                        int *, hipStream_t);
+template hipError_t coldot_part<float>(int64_t, int, const float *, int64_t, const float *, int64_t, float *, int *,
+                                       hipStream_t);
 
 #define GCGE_CG_INST(T)                                                                                          \
     template hipError_t cg_init<T>(const double *, int64_t, const double *, int, int64_t, T *, T *, T *, int64_t, \
@@ -1626,6 +1635,8 @@ template hipError_t copy_cols<float, double>(int64_t, int, const float *, int64_
                                              const double *, hipStream_t);
 template hipError_t copy_cols<double, float>(int64_t, int, const double *, int64_t, float *, int64_t,
                                              const double *, hipStream_t);
+template hipError_t copy_cols<float, float>(int64_t, int, const float *, int64_t, float *, int64_t,
+                                            const double *, hipStream_t);
 
 // one thread per row; columns move left in increasing order, so a source is
 // always read before its slot is overwritten
@@ -1796,9 +1807,9 @@ hipError_t scatter_values(int64_t nnz, const int32_t *map, const double *src, do
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_scale_rows(int64_t n, int k, const double *__restrict__ d,
-                                                    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y,
-                                                    int64_t ldy) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_rows(int64_t n, int k, const T *__restrict__ d, const T *__restrict__ X,
+                                                    int64_t ldx, T *__restrict__ Y, int64_t ldy) {
     const int64_t total = n * k;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
         const int64_t i = t / k;
@@ -1807,12 +1818,16 @@ __global__ __launch_bounds__(256) void k_scale_rows(int64_t n, int k, const doub
     }
 }
 
-hipError_t scale_rows(int64_t n, int k, const double *d, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                      hipStream_t st) {
+template <typename T>
+hipError_t scale_rows(int64_t n, int k, const T *d, const T *X, int64_t ldx, T *Y, int64_t ldy, hipStream_t st) {
     if (n == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scale_rows, dim3(ew_grid(n * k)), dim3(256), 0, st, n, k, d, X, ldx, Y, ldy);
+    hipLaunchKernelGGL(k_scale_rows<T>, dim3(ew_grid(n * k)), dim3(256), 0, st, n, k, d, X, ldx, Y, ldy);
     return hipGetLastError();
 }
+template hipError_t scale_rows<double>(int64_t, int, const double *, const double *, int64_t, double *, int64_t,
+                                       hipStream_t);
+template hipError_t scale_rows<float>(int64_t, int, const float *, const float *, int64_t, float *, int64_t,
+                                      hipStream_t);
 
 // ---------------------------------------------------------------------------
 // workspace

@@ -167,17 +167,16 @@ struct CgRunner {
     }
     // Preconditioned CG (M^-1 = the multigrid V-cycle) on M delta = R, delta
     // from 0; same stopping rule as run().  z is one more n x ld vector.
-    int run_pcg(const DevCsr<T> &M, Amg &amg, const double *R, int64_t ldr, int k, int maxit, double rel_tol, T *x,
-                T *r, T *p, T *q, T *z, int64_t ld, CgState<T> cs, int64_t *total_its) {
-        static_assert(sizeof(T) == sizeof(double), "the V-cycle is FP64");
+    int run_pcg(const DevCsr<T> &M, Amg &amg, const double *R, int64_t ldr, const double *rscale, int k, int maxit,
+                double rel_tol, T *x, T *r, T *p, T *q, T *z, int64_t ld, CgState<T> cs, int64_t *total_its) {
         hipError_t e = ws.ensure_part(sizeof(double) * (size_t)k * max_row_parts() + 256);
         if (e != hipSuccess) return fail(e, "workspace");
         T *part = (T *)ws.part;
         int nparts = 0;
-        e = cg_init<T>(R, ldr, nullptr, k, n, r, p, x, ld, part, &nparts, cs, st);
+        e = cg_init<T>(R, ldr, rscale, k, n, r, p, x, ld, part, &nparts, cs, st);
         if (e == hipSuccess) e = cg_init_finish<T>(part, nparts, k, cs, st);
         if (e != hipSuccess) return fail(e, "pcg init");
-        int rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err);
+        int rc = amg.apply<T>(r, ld, k, z, ld, part, &nparts, st, err);
         if (rc) return rc;
         e = pcg_rz<T>(part, nparts, k, true, cs, st);
         if (e == hipSuccess) e = copy_cols<T, T>(n, k, z, ld, p, ld, nullptr, st);
@@ -195,7 +194,7 @@ struct CgRunner {
             if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
             if (e != hipSuccess) return fail(e, "pcg iteration");
             pb = prof ? prof->begin(st) : -1;
-            rc = amg.apply(r, ld, k, z, ld, part, &nparts, st, err, cs.flags);
+            rc = amg.apply<T>(r, ld, k, z, ld, part, &nparts, st, err, cs.flags);
             if (prof) prof->end(6, pb, k, st);
             if (rc) return rc;
             e = pcg_rz<T>(part, nparts, k, false, cs, st);
@@ -269,7 +268,7 @@ struct gcge_handle_s {
     double *Wb = nullptr, *AWb = nullptr, *BWb = nullptr, *Rb = nullptr;
     int64_t ldB = 0;
     double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};
-    float *cg32[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *cg32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void *cgmem = nullptr;
     double *mval = nullptr;
     float *mval32 = nullptr;
@@ -378,7 +377,7 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
         for (int i = 0; i < (prec >= 2 ? 4 : 3); ++i) A((void **)&cg64[i], sizeof(double) * n * ldB);
     } else {
         A((void **)&mval32, sizeof(float) * std::max<int64_t>(op.nnz, 1));
-        for (int i = 0; i < 4; ++i) A((void **)&cg32[i], sizeof(float) * n * ldB);
+        for (int i = 0; i < (prec >= 2 ? 5 : 4); ++i) A((void **)&cg32[i], sizeof(float) * n * ldB);
     }
     A(&cgmem, 8 * sizeof(double) * (ldB + 16) + 64);
     if (e != hipSuccess) {
@@ -471,8 +470,8 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
                 amg_setup_ms = ms_since(ta);
             }
             cs.rz = (double *)(cm + 7 * slot);
-            return runner.run_pcg(M, amg, Rb, ldB, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2],
-                                  cg64[3], ldB, cs, cg_its);
+            return runner.run_pcg(M, amg, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1],
+                                  cg64[2], cg64[3], ldB, cs, cg_its);
         }
         return runner.run(M, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
                           cg_its);
@@ -493,8 +492,25 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
                       (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
     CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
     DevCsr<float> M = op.csr_of(mval32);
-    int rc = runner.run(M, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
+    int rc;
+    if (precond) {
+        // FP32 preconditioned CG with the FP32 copy of the V-cycle (the
+        // hierarchy is built from the FP64 operator; level 0 is M itself)
+        if (!amg_valid) {
+            const auto ta = Clock::now();
+            rc = amg.build(op.A_csr(), amg_levels, amg_coarse, st, err);
+            if (rc) return rc;
+            amg_valid = true;
+            amg_setup_ms = ms_since(ta);
+        }
+        amg.set_level0_f32(M);
+        cs.rz = (float *)(cm + 7 * slot);
+        rc = runner.run_pcg(M, amg, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3],
+                            cg32[4], ldB, cs, cg_its);
+    } else {
+        rc = runner.run(M, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
                         cg_its);
+    }
     if (rc) return rc;
     e = copy_cols<float, double>(op.n, k, cg32[0], ldB, Wb, ldB, dusc, st);
     if (e != hipSuccess) return hipfail(e, "cg output");
@@ -521,8 +537,6 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     const int sizeX = (int)sx;
     const int nx0 = mv ? (int)std::min<int64_t>(3 * (int64_t)bs, n) : sizeX;
     if (x0_k > nx0) return fail(GCGE_ERR_INVALID_ARG, "more initial vectors than the initial block holds");
-    if (precond && precision != GCGE_PREC_FP64)
-        return fail(GCGE_ERR_INVALID_ARG, "the multigrid preconditioner runs with precision fp64");
     int rc = ensure_buffers(bs, nx0, precision + 2 * precond);
     if (rc) return rc;
     stg.st = st;
@@ -1322,7 +1336,7 @@ extern "C" int gcge_amg_apply(gcge_amg h, const double *B, int64_t ldb, int k, d
     try {
         std::lock_guard<std::mutex> lk(h->mu);
         hipStream_t st = (hipStream_t)stream;
-        const int rc = h->amg.apply(B, ldb, k, Y, ldy, nullptr, nullptr, st, h->err);
+        const int rc = h->amg.apply<double>(B, ldb, k, Y, ldy, nullptr, nullptr, st, h->err);
         if (rc) return step_fail(rc, h->err);
         return GCGE_OK;
     } catch (...) {
@@ -1370,8 +1384,8 @@ extern "C" int gcge_pcg(const gcge_csr *A, gcge_amg M, const double *R, int64_t 
                                (double *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                (int *)(c8 + 6 * slot), (double *)(c8 + 7 * slot)};
             CgRunner<double> runner{n, C.ws, st, nullptr, nullptr, err};
-            rc = runner.run_pcg(op.csr_of(m64), M->amg, R, ldr, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld,
-                                v + 3 * n * ld, v + 4 * n * ld, ld, cs, nullptr);
+            rc = runner.run_pcg(op.csr_of(m64), M->amg, R, ldr, nullptr, k, maxit, rel_tol, v, v + n * ld,
+                                v + 2 * n * ld, v + 3 * n * ld, v + 4 * n * ld, ld, cs, nullptr);
             if (!rc) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
             if (!rc && e == hipSuccess && its) e = C.stg.download(its, cs.its, sizeof(int) * k);
         }

@@ -247,9 +247,12 @@ def test_solver_with_multigrid_matches_oracle(g, name, make, nev, bs):
     assert st["max_rel_residual"] <= 1e-8
 
 
-def test_solver_multigrid_rejects_mixed_precision(g):
-    A = wl.laplace2d_5pt(16)
+def test_solver_multigrid_mixed_precision_matches_fp64(g):
+    A = wl.laplace3d_7pt(10)
+    d = wl.diag_uniform(A.n)
+    ref = orc.pencil_eigs(A, "diag", d, 26)[0][:20]
     Ad = g.DeviceCsr.from_csr(A)
-    with g.Solver(Ad, None, 4, 1e-8, block_size=4, precond=1, precision=1) as s:
-        with pytest.raises(g.GcgeError):
-            s.solve()
+    with g.Solver(Ad, dev(d), 20, 1e-8, block_size=5, precond=1, precision=1, amg_coarse=64) as s:
+        lam, X, st = s.solve()
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    assert st["max_rel_residual"] <= 1e-8
