@@ -195,7 +195,7 @@ const char *gcge_last_error(gcge_handle h);
 
 /* Y = A X (CSR times a block of k vectors; Section 3.4, the product of the
  * matrix with a multi-vector).  X: n x k (ldx), Y: n x k (ldy), device, no
- * overlap.  k >= 0. */
+ * overlap.  k >= 0.  Only the k columns of each row of Y are written. */
 int gcge_spmm(const gcge_csr *A, const double *X, int64_t ldx, int k, double *Y, int64_t ldy, void *stream);
 
 /* FP32 variant used by the mixed-precision inner CG: values, X and Y float,
@@ -205,12 +205,15 @@ int gcge_spmm_f32(int64_t n, const int32_t *rowptr, const int32_t *colind, const
 
 /* Column j of Y is (A - sigma[j] B) x_j; sigma: host double[k].  This is the
  * operator of STEP 6 (sigma_j = theta) and of the STEP 4 residual
- * (sigma_j = lambda_j).  For GCGE_B_CSR, B's pattern may differ from A's. */
+ * (sigma_j = lambda_j).  For GCGE_B_CSR, B's pattern may differ from A's.
+ * Like the solver's internal blocks, an odd k with an even ldy and 16-byte
+ * aligned rows may also overwrite column k of each row of Y (padding). */
 int gcge_shifted_spmm(const gcge_csr *A, int b_kind, const void *B, const double *sigma,
                       const double *X, int64_t ldx, int k, double *Y, int64_t ldy, void *stream);
 
 /* STEP 4: R = A X - B X diag(lam) and per-column norms rnorm[j] = ||r_j||_2,
- * bxnorm[j] = ||B x_j||_2.  lam, rnorm, bxnorm: host double[k]. */
+ * bxnorm[j] = ||B x_j||_2.  lam, rnorm, bxnorm: host double[k].  Padding as
+ * gcge_shifted_spmm. */
 int gcge_residual(const gcge_csr *A, int b_kind, const void *B, const double *lam,
                   const double *X, int64_t ldx, int k, double *R, int64_t ldr,
                   double *rnorm, double *bxnorm, void *stream);

@@ -252,7 +252,8 @@ __device__ __forceinline__ void vst_nt(T *p, const Vec<T, V> &x) {
 // gathered vector rows being requested before they are used.  Requires
 // 16-byte aligned rows and leading dimensions that cover round_up(k, V)
 // columns: the tail lane reads padding columns of the inputs (never part of a
-// result) but writes only the columns below k.
+// result); it writes the padding columns of the output too, except in the
+// affine mode, whose outputs can be caller-owned blocks.
 template <typename T, int G, int V, int MODE, int RED>
 __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ colind, const T *__restrict__ va,
@@ -384,12 +385,12 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc.v[v] = fma(w, bb.v[v] - acc.v[v], zz.v[v]);
             }
-            if (c0 + V <= k) {
-                vst_nt<T, V>(Y + row * ldy + c0, acc);
-            } else {   // tail lane: the padding columns of Y are left untouched
+            if (MODE == 3 && c0 + V > k) {   // tail lane: the padding columns of Y are left untouched
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (c0 + v < k) Y[row * ldy + c0 + v] = acc.v[v];
+            } else {
+                vst_nt<T, V>(Y + row * ldy + c0, acc);
             }
             if (RED == 1) {
 #pragma unroll

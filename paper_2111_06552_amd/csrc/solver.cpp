@@ -1050,8 +1050,9 @@ extern "C" int gcge_spmm(const gcge_csr *A, const double *X, int64_t ldx, int k,
     hipStream_t st = (hipStream_t)stream;
     for (int c0 = 0; c0 < k; c0 += 128) {
         const int kk = std::min(128, k - c0);
-        hipError_t e = spmm<double>(to_dev(A), nullptr, nullptr, nullptr, 0, 0, X + c0, ldx, kk, Y + c0, ldy, nullptr,
-                                    0, nullptr, nullptr, st);
+        Affine<double> exact;   // Y = 0 - (-1) A X: the affine epilogue writes only the k columns
+        exact.ws = -1.0;
+        hipError_t e = spmm_affine<double>(to_dev(A), X + c0, ldx, kk, Y + c0, ldy, exact, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm");
     }
     return GCGE_OK;
@@ -1065,8 +1066,9 @@ extern "C" int gcge_spmm_f32(int64_t n, const int32_t *rowptr, const int32_t *co
     DevCsr<float> A{n, 0, rowptr, colind, val};
     for (int c0 = 0; c0 < k; c0 += 128) {
         const int kk = std::min(128, k - c0);
-        hipError_t e = spmm<float>(A, nullptr, nullptr, nullptr, 0, 0, X + c0, ldx, kk, Y + c0, ldy, nullptr, 0,
-                                   nullptr, nullptr, st);
+        Affine<float> exact;   // Y = 0 - (-1) A X: the affine epilogue writes only the k columns
+        exact.ws = -1.0f;
+        hipError_t e = spmm_affine<float>(A, X + c0, ldx, kk, Y + c0, ldy, exact, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm_f32");
     }
     return GCGE_OK;
