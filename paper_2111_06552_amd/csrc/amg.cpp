@@ -428,7 +428,7 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
 
 template <typename T>
 int Amg::apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *nparts, hipStream_t st,
-               std::string &err, const int *skip) {
+               std::string &err, const int *skip, bool exact_out) {
     constexpr bool F32 = std::is_same<T, float>::value;
     if (lv.empty()) {
         err = "amg: no hierarchy";
@@ -552,6 +552,7 @@ int Amg::apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *
         sm.ldz = ldw;
         sm.w = w_of(l);
         sm.ws = T(1);
+        sm.exact = l == 0 && exact_out;
         T *out = l == 0 ? y : Y[l];
         const int64_t ldo = l == 0 ? ldy : ldw;
         if (e == hipSuccess) {
@@ -568,8 +569,8 @@ int Amg::apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *
     return GCGE_OK;
 }
 template int Amg::apply<double>(const double *, int64_t, int, double *, int64_t, double *, int *, hipStream_t,
-                                std::string &, const int *);
+                                std::string &, const int *, bool);
 template int Amg::apply<float>(const float *, int64_t, int, float *, int64_t, float *, int *, hipStream_t,
-                               std::string &, const int *);
+                               std::string &, const int *, bool);
 
 }  // namespace gcge

@@ -88,6 +88,9 @@ int max_row_parts();
 // or z reads as zero.  The multigrid V-cycle uses it for the residual
 // (z = 0, w = 1), the damped Jacobi sweep (z = x, w = omega / a_ii) and the
 // coarse-grid correction (A = P, b = 0, z = x, w = -1, in place).
+// With exact, only the k columns of each output row are written (outputs
+// owned by a caller); otherwise padding columns up to round_up(k, 16 / sizeof(T))
+// may be written too (the library's own blocks), which keeps 16-byte stores.
 template <typename T>
 struct Affine {
     const T *b = nullptr;
@@ -96,6 +99,7 @@ struct Affine {
     int64_t ldz = 0;
     const T *w = nullptr;
     T ws = T(1);
+    bool exact = false;
 };
 // With zdot != nullptr the SpMM also writes partials of the column dots
 // y . zdot (part[c * np + g], np in *nparts), as the RED = 2 products do.
@@ -239,9 +243,10 @@ struct Amg {
     // when skip[0] == 0 (the CG's count of active columns).
     // T = float runs the cycle on the FP32 copies (the coarsest solve in FP64);
     // it needs the FP32 level-0 operator from set_level0_f32.
+    // exact_out: y is caller-owned, its padding columns are not written.
     template <typename T>
     int apply(const T *b, int64_t ldb, int k, T *y, int64_t ldy, T *part, int *nparts, hipStream_t st,
-              std::string &err, const int *skip = nullptr);
+              std::string &err, const int *skip = nullptr, bool exact_out = false);
     void set_level0_f32(const DevCsr<float> &A32) { if (!lv.empty()) lv[0].A32 = A32; }
     void release();
     ~Amg() { release(); }

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int32_t *__restri
             } else if (MODE == 2) {
                 bx = accb[t];
                 y = fma(-sg[t], bx, y);
-            } else if (MODE == 3) {
+            } else if (MODE >= 3) {
                 const T w = af.w != nullptr ? af.ws * af.w[row] : af.ws;
                 const T bb = af.b != nullptr ? af.b[row * af.ldb + col[t]] : T(0);
                 const T zz = af.z != nullptr ? af.z[row * af.ldz + col[t]] : T(0);
@@ -252,8 +252,8 @@ __device__ __forceinline__ void vst_nt(T *p, const Vec<T, V> &x) {
 // gathered vector rows being requested before they are used.  Requires
 // 16-byte aligned rows and leading dimensions that cover round_up(k, V)
 // columns: the tail lane reads padding columns of the inputs (never part of a
-// result); it writes the padding columns of the output too, except in the
-// affine mode, whose outputs can be caller-owned blocks.
+// result); it writes the padding columns of the output too, except in MODE 4
+// (the affine epilogue for caller-owned outputs).
 template <typename T, int G, int V, int MODE, int RED>
 __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ colind, const T *__restrict__ va,
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                     bx[v] = accb.v[v];
                     acc.v[v] = fma(-sg[v], bx[v], acc.v[v]);
                 }
-            } else if (MODE == 3) {
+            } else if (MODE >= 3) {
                 const T w = af.w != nullptr ? af.ws * af.w[row] : af.ws;
                 Vec<T, V> bb, zz;
 #pragma unroll
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc.v[v] = fma(w, bb.v[v] - acc.v[v], zz.v[v]);
             }
-            if (MODE == 3 && c0 + V > k) {   // tail lane: the padding columns of Y are left untouched
+            if (MODE == 4 && c0 + V > k) {   // tail lane: the padding columns of Y are left untouched
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (c0 + v < k) Y[row * ldy + c0 + v] = acc.v[v];
@@ -540,9 +540,15 @@ hipError_t spmm_affine(const DevCsr<T> &A, const T *X, int64_t ldx, int k, T *Y,
     if (k > 128) return hipErrorInvalidValue;
     if (zdot != nullptr) {
         if (part == nullptr || nparts == nullptr) return hipErrorInvalidValue;
+        if (af.exact)
+            return spmm_dispatch<T, 4, 2>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, zdot, ldzdot, part,
+                                          nparts, skip, st, af);
         return spmm_dispatch<T, 3, 2>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, zdot, ldzdot, part, nparts,
                                       skip, st, af);
     }
+    if (af.exact)
+        return spmm_dispatch<T, 4, 0>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, nullptr, 0, nullptr, nullptr,
+                                      skip, st, af);
     return spmm_dispatch<T, 3, 0>(A, nullptr, nullptr, nullptr, X, ldx, k, Y, ldy, nullptr, 0, nullptr, nullptr,
                                   skip, st, af);
 }

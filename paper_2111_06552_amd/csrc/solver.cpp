@@ -1052,6 +1052,7 @@ extern "C" int gcge_spmm(const gcge_csr *A, const double *X, int64_t ldx, int k,
         const int kk = std::min(128, k - c0);
         Affine<double> exact;   // Y = 0 - (-1) A X: the affine epilogue writes only the k columns
         exact.ws = -1.0;
+        exact.exact = true;
         hipError_t e = spmm_affine<double>(to_dev(A), X + c0, ldx, kk, Y + c0, ldy, exact, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm");
     }
@@ -1068,6 +1069,7 @@ extern "C" int gcge_spmm_f32(int64_t n, const int32_t *rowptr, const int32_t *co
         const int kk = std::min(128, k - c0);
         Affine<float> exact;   // Y = 0 - (-1) A X: the affine epilogue writes only the k columns
         exact.ws = -1.0f;
+        exact.exact = true;
         hipError_t e = spmm_affine<float>(A, X + c0, ldx, kk, Y + c0, ldy, exact, st);
         if (e != hipSuccess) return step_hip(e, "gcge_spmm_f32");
     }
@@ -1338,7 +1340,7 @@ extern "C" int gcge_amg_apply(gcge_amg h, const double *B, int64_t ldb, int k, d
     try {
         std::lock_guard<std::mutex> lk(h->mu);
         hipStream_t st = (hipStream_t)stream;
-        const int rc = h->amg.apply<double>(B, ldb, k, Y, ldy, nullptr, nullptr, st, h->err);
+        const int rc = h->amg.apply<double>(B, ldb, k, Y, ldy, nullptr, nullptr, st, h->err, nullptr, true);
         if (rc) return step_fail(rc, h->err);
         return GCGE_OK;
     } catch (...) {
