@@ -94,6 +94,20 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
             "algorithmic_flops_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": p["launches"]}
 
 
+def cg_iteration_roofline(kr):
+    """One full-block CG iteration (its three kernels) as one HBM-bound step:
+    the sum of their algorithmic bytes over the sum of their average
+    full-block launch times."""
+    parts = [kr.get(c) for c in ("cg_spmm", "cg_update_r", "cg_update_xp")]
+    if any(p is None for p in parts):
+        return None
+    b = sum(p["algorithmic_bytes_per_launch"] for p in parts)
+    ms = sum(p["avg_launch_ms"] for p in parts)
+    achieved = b / (ms * 1e-3) / 1e9
+    return {"kernels": "SpMM + r update + x/p update", "bound": "hbm", "algorithmic_bytes": b, "ms": ms,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+
+
 def dominant_roofline(prof, n, nnz, s=8, bs=None):
     """Roofline entry of the kernel class with the largest summed device time."""
     name = max(prof, key=lambda c: prof[c]["ms"])
@@ -321,6 +335,7 @@ def main():
     out["roofline"] = roof
     out["kernel_rooflines"] = {c: class_roofline(c, prof[c], A.n, A.nnz, bs=bs) for c in prof}
     out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"] / args.steps, 2) for c in prof}
+    out["cg_iteration_roofline"] = cg_iteration_roofline(out["kernel_rooflines"])
     if not args.no_mixed:
         tm, sm, lamm = run("mixed", args.steps, args.warmup)
         out["mixed"] = {"value": float(tm.mean()), "unit": "s", "ms_per_step": float(tm.mean() * 1e3),
@@ -331,6 +346,7 @@ def main():
         profm = sum_prof(sm)
         out["mixed"]["kernel_rooflines"] = {c: class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs)
                                             for c in ("cg_spmm", "cg_update_r", "cg_update_xp")}
+        out["mixed"]["cg_iteration_roofline"] = cg_iteration_roofline(out["mixed"]["kernel_rooflines"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, int(st["spmm_columns"]), args.cpu_budget_s)
     print(json.dumps(out), flush=True)
