@@ -98,6 +98,24 @@ def test_config4_mixed_matches_fp64_full(config2):
     check_sampled(A, "diag", B, lam, X, sampled_columns(p["nev"], 24, 72), p["tol"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config2_multigrid_inner_solve_full(g, config2, prec):
+    # STEP 6 as PCG at theta = 0 with the multigrid V-cycle (Section 2's
+    # suggestion): the same 200 eigenpairs as the FP64 shifted-CG solve.
+    A, B, p, out = config2
+    lam64 = out["fp64"][0]
+    Ad = g.DeviceCsr.from_csr(A)
+    Bd = torch.as_tensor(B, dtype=torch.float64, device="cuda")
+    with g.Solver(Ad, Bd, p["nev"], p["tol"], block_size=p["block_size"], precision=prec, precond=1) as s:
+        lam, X, st = s.solve()
+        lam, X = lam.numpy().copy(), host(X)
+    print(f"[config2 multigrid] {prec}: {st['iterations']} iterations, {st['cg_iterations']} PCG iterations, "
+          f"max residual {st['max_rel_residual']:.2e}", flush=True)
+    assert st["status"] == 0 and st["nconv"] == p["nev"]
+    assert np.max(np.abs(lam - lam64) / np.abs(lam64)) < 1e-10
+    check_sampled(A, "diag", B, lam, X, sampled_columns(p["nev"], 12, 73), p["tol"])
+
+
 def test_config2_identity_B_closed_form_full(g):
     """128^3 Laplacian with B = I: the 200 smallest eigenvalues are known exactly
     (the 6-fold cluster 197-202 is cut by nev; eigenvalues are still unique)."""
