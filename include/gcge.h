@@ -142,6 +142,7 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *                         aggregation cannot coarsen) is returned by gcge_solve.
  *  "amg_levels"   [10]    level limit of that hierarchy (1 .. 16)
  *  "amg_coarse"   [512]   rows at or below which a level is the coarsest (1 .. 4096)
+ * (double option "amg_strength" [0.02]: the strength threshold of the hierarchy)
  * Unknown keys or out-of-range values return INVALID_ARG. */
 int gcge_set_option_i(gcge_handle h, const char *key, int64_t value);
 
@@ -297,7 +298,8 @@ int gcge_p_hat(int dim, int nx, const double *xhat, int shift, int n_old, int n_
  * suggests algebraic multigrid as the preconditioner of STEP 6 with theta = 0
  * when A discretizes a PDE; the paper does not fix the method, so this is
  * smoothed aggregation (Vanek, Mandel, Brezina 1996):
- *   strength   |a_ij| >= eps_l sqrt(a_ii a_jj), eps_l = 0.08 * 2^-l at level l;
+ *   strength   |a_ij| >= eps_l sqrt(a_ii a_jj), eps_l = strength * 2^-l at level l
+ *              (0 <= strength < 1; 0.02 suits 7- and 27-point stencils);
  *   aggregates rows in order: a row whose strong neighbours are all free
  *              seeds an aggregate with them; a row left joins the aggregate
  *              of its strongest already aggregated neighbour (first in column
@@ -317,10 +319,12 @@ typedef struct gcge_amg_s *gcge_amg;
  * operator is read from it at every gcge_amg_apply / gcge_pcg, so it must
  * stay alive and unchanged until gcge_amg_destroy).  The setup runs on the
  * host (A is copied down once); the coarse levels live in device memory owned
- * by the handle.  max_levels in 1 .. 16, coarse_max in 1 .. 4096.  Errors:
+ * by the handle.  max_levels in 1 .. 16, coarse_max in 1 .. 4096, strength
+ * in [0, 1).  Errors:
  * INVALID_ARG, NOT_SPD (a non-positive diagonal entry, or a coarsest level
  * that is not positive definite), OOM, HIP. */
-int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, void *stream, gcge_amg *out);
+int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, double strength, void *stream,
+                    gcge_amg *out);
 
 /* Number of levels (the last one is the dense coarsest level) and, for the
  * first min(levels, cap), the rows and stored entries of each level operator

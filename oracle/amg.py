@@ -7,7 +7,10 @@ use smoothed aggregation (Vanek, Mandel and Brezina, Computing 56, 1996) with
 the choices below, so that both sides compute the same preconditioner:
 
 * strength of connection at level l: j != i is strong for row i when
-  |a_ij| >= eps_l * sqrt(|a_ii a_jj|), eps_l = 0.08 * 0.5**l;
+  |a_ij| >= eps_l * sqrt(|a_ii a_jj|), eps_l = eps_0 * 0.5**l with eps_0 =
+  0.02 by default (the 27-point Q1 stiffness couples a row to each neighbour
+  by about 1/30 of its diagonal, below the 0.08 of the textbook Laplacian
+  setting);
 * greedy aggregation in row order, two phases:
   1. a row whose strong neighbours are all unaggregated starts an aggregate
      with them (a row without strong neighbours becomes a singleton);
@@ -43,7 +46,7 @@ import numpy as np
 
 from .core import cholesky, solve_lower, solve_lower_t, spmm
 
-STRENGTH_EPS0 = 0.08
+STRENGTH_EPS0 = 0.02
 TIE_REL = 1e-8
 MAX_ROW_FILL = 400
 
@@ -175,7 +178,7 @@ def _from_dense(D):
     return SparseRows(rp, ci, va, D.shape[1])
 
 
-def amg_setup(A, coarse_max=512, max_levels=10):
+def amg_setup(A, coarse_max=512, max_levels=10, strength=STRENGTH_EPS0):
     """Smoothed-aggregation hierarchy of A (dense products: small sizes only).
 
     Returns a list of level dicts: ``A`` (CSR of the level operator), ``Ad``
@@ -193,7 +196,7 @@ def amg_setup(A, coarse_max=512, max_levels=10):
         L = {"A": cur, "Ad": Ad, "dinv": 1.0 / d, "n": cur.n}
         last = cur.n <= coarse_max or lev == max_levels - 1 or cur.nnz > MAX_ROW_FILL * cur.n
         if not last:
-            agg, nagg = aggregate(cur, STRENGTH_EPS0 * 0.5 ** lev)
+            agg, nagg = aggregate(cur, strength * 0.5 ** lev)
             if 2 * nagg > cur.n:
                 last = True
         if last:

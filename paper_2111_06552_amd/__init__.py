@@ -97,7 +97,7 @@ def _b_args(B):
 _INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
              "dense_eig", "orth", "orth_block", "precond", "amg_levels", "amg_coarse",
              "profile"}
-_DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol"}
+_DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol", "amg_strength"}
 
 
 class Solver:
@@ -346,11 +346,11 @@ class Amg:
 
     Keeps a reference to A: its device arrays are the level-0 operator."""
 
-    def __init__(self, A: DeviceCsr, max_levels: int = 10, coarse_max: int = 512):
+    def __init__(self, A: DeviceCsr, max_levels: int = 10, coarse_max: int = 512, strength: float = 0.02):
         self._A = A
         self._c = A.c()
         h = ctypes.c_void_p()
-        _lib.check(_L().gcge_amg_create(ctypes.byref(self._c), int(max_levels), int(coarse_max),
+        _lib.check(_L().gcge_amg_create(ctypes.byref(self._c), int(max_levels), int(coarse_max), float(strength),
                                         ctypes.c_void_p(_stream(A.rowptr.device)), ctypes.byref(h)))
         self._h = h
 

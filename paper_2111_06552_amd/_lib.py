@@ -114,7 +114,7 @@ def load():
             "gcge_p_hat": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_int, c_double, c_void_p, c_void_p]),
             "gcge_pattern_grad": (c_int, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_void_p,
                                           c_void_p, c_void_p]),
-            "gcge_amg_create": (c_int, [P(Csr), c_int, c_int, c_void_p, P(c_void_p)]),
+            "gcge_amg_create": (c_int, [P(Csr), c_int, c_int, c_double, c_void_p, P(c_void_p)]),
             "gcge_amg_levels": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p, c_int]),
             "gcge_amg_aggregates": (c_int, [c_void_p, c_int, c_void_p]),
             "gcge_amg_apply": (c_int, [c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int64, c_void_p]),

@@ -4,7 +4,9 @@
 // The paper does not fix the AMG; this one is smoothed aggregation (Vanek,
 // Mandel and Brezina, Computing 56, 1996) with these choices:
 //   strength      j != i is strong for row i when |a_ij| >= eps_l sqrt(|a_ii a_jj|),
-//                 eps_l = 0.08 * 2^-l at level l;
+//                 eps_l = eps_0 * 2^-l at level l (eps_0 = 0.02 by default: the
+//                 27-point Q1 stiffness couples a row to each neighbour by
+//                 about 1/30 of its diagonal);
 //   aggregation   rows in order; phase 1: a row whose strong neighbours are all
 //                 free seeds an aggregate with them (no strong neighbour: a
 //                 singleton); phase 2: a row left joins the phase-1 aggregate
@@ -41,7 +43,6 @@ namespace gcge {
 
 namespace {
 
-constexpr double STRENGTH_EPS0 = 0.08;
 constexpr double TIE_REL = 1e-8;
 
 int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP; }
@@ -325,9 +326,11 @@ void Amg::release() {
     rho.clear();
 }
 
-int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStream_t st, std::string &err) {
+int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, double strength, hipStream_t st,
+               std::string &err) {
     release();
-    if (max_levels < 1 || max_levels > AMG_MAX_LEVELS || coarse_max < 1 || A0.n < 1) {
+    if (max_levels < 1 || max_levels > AMG_MAX_LEVELS || coarse_max < 1 || A0.n < 1 || !(strength >= 0.0) ||
+        strength >= 1.0) {
         err = "amg: invalid setup parameters";
         return GCGE_ERR_INVALID_ARG;
     }
@@ -368,7 +371,7 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStre
         std::vector<int32_t> ag;
         int64_t nagg = 0;
         if (!last) {
-            aggregate(cur, d, STRENGTH_EPS0 * std::ldexp(1.0, -lev), ag, nagg);
+            aggregate(cur, d, strength * std::ldexp(1.0, -lev), ag, nagg);
             if (2 * nagg > cur.n) last = true;
         }
         if (last) {

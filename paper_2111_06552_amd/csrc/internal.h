@@ -234,7 +234,8 @@ struct Amg {
     int kcap = 0;
     int64_t ldw = 0;
     // A0: device CSR of the level-0 operator (borrowed; must outlive the hierarchy).
-    int build(const DevCsr<double> &A0, int max_levels, int coarse_max, hipStream_t st, std::string &err);
+    int build(const DevCsr<double> &A0, int max_levels, int coarse_max, double strength, hipStream_t st,
+              std::string &err);
     // y = V(b) for k <= 128 columns (b and y n x k row-major, 16-byte aligned
     // rows when ldb, ldy are even).  With part != nullptr the last kernel also
     // writes per-work-group partials of the column dots b . y (part[c * np + g],
@@ -254,6 +255,7 @@ struct Amg {
 constexpr int AMG_MAX_LEVELS = 16;
 constexpr int64_t AMG_COARSE_LIMIT = 4096;   // largest coarsest level (dense inverse)
 constexpr int64_t AMG_MAX_ROW_FILL = 400;    // a level denser than this is not coarsened further
+constexpr double AMG_STRENGTH = 0.02;        // default strength threshold at the finest level
 
 // ------------------------------------------------------------- host dense
 // Symmetric eigensolver: a (n x n, row-major, destroyed), w ascending, z (n x

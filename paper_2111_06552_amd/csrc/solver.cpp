@@ -245,6 +245,7 @@ struct gcge_handle_s {
     int64_t opt_bs = 0, opt_sizex = 0;
     int max_iter = 1000, cg_max_iter = 30, precision = GCGE_PREC_FP64, moving = 0, shift = 1, check = 1;
     int precond = 0, amg_levels = 10, amg_coarse = 512;   // STEP 6 preconditioner (1: multigrid at theta = 0)
+    double amg_strength = AMG_STRENGTH;
     Amg amg;
     bool amg_valid = false;
     double amg_setup_ms = 0.0;
@@ -464,7 +465,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
         if (precond) {
             if (!amg_valid) {
                 const auto ta = Clock::now();
-                int rc = amg.build(op.A_csr(), amg_levels, amg_coarse, st, err);
+                int rc = amg.build(op.A_csr(), amg_levels, amg_coarse, amg_strength, st, err);
                 if (rc) return rc;
                 amg_valid = true;
                 amg_setup_ms = ms_since(ta);
@@ -498,7 +499,7 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
         // hierarchy is built from the FP64 operator; level 0 is M itself)
         if (!amg_valid) {
             const auto ta = Clock::now();
-            rc = amg.build(op.A_csr(), amg_levels, amg_coarse, st, err);
+            rc = amg.build(op.A_csr(), amg_levels, amg_coarse, amg_strength, st, err);
             if (rc) return rc;
             amg_valid = true;
             amg_setup_ms = ms_since(ta);
@@ -913,13 +914,18 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
 extern "C" int gcge_set_option_d(gcge_handle h, const char *key, double v) {
     if (!h || !key) return GCGE_ERR_INVALID_ARG;
     const std::string k(key);
-    const bool zero_ok = (k == "cg_rel_tol");   // 0: every column takes cg_max_iter iterations
+    const bool zero_ok = (k == "cg_rel_tol" || k == "amg_strength");   // cg_rel_tol 0: fixed CG length
     if (!std::isfinite(v) || v < 0.0 || (v == 0.0 && !zero_ok))
         return h->fail(GCGE_ERR_INVALID_ARG, "bad value for option " + k);
     if (k == "tol") h->tol = v;
     else if (k == "cg_rel_tol") h->cg_rel_tol = v;
     else if (k == "orth_tol") h->orth_tol = v;
     else if (k == "drop_tol") h->drop_tol = v;
+    else if (k == "amg_strength") {
+        if (v >= 1.0) return h->fail(GCGE_ERR_INVALID_ARG, "bad value for option " + k);
+        h->amg_strength = v;
+        h->amg_valid = false;
+    }
     else return h->fail(GCGE_ERR_INVALID_ARG, "unknown option " + k);
     return GCGE_OK;
 }
@@ -1293,15 +1299,16 @@ struct gcge_amg_s {
     std::string err;
 };
 
-extern "C" int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, void *stream, gcge_amg *out) {
+extern "C" int gcge_amg_create(const gcge_csr *A, int max_levels, int coarse_max, double strength, void *stream,
+                               gcge_amg *out) {
     if (!out) return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_create: out is null");
     *out = nullptr;
     if (!A || !csr_ok(A) || max_levels < 1 || max_levels > AMG_MAX_LEVELS || coarse_max < 1 ||
-        coarse_max > AMG_COARSE_LIMIT)
+        coarse_max > AMG_COARSE_LIMIT || !(strength >= 0.0) || strength >= 1.0)
         return step_fail(GCGE_ERR_INVALID_ARG, "gcge_amg_create: invalid argument");
     try {
         gcge_amg_s *h = new gcge_amg_s;
-        const int rc = h->amg.build(to_dev(A), max_levels, coarse_max, (hipStream_t)stream, h->err);
+        const int rc = h->amg.build(to_dev(A), max_levels, coarse_max, strength, (hipStream_t)stream, h->err);
         if (rc) {
             const std::string m = h->err;
             delete h;

@@ -92,7 +92,7 @@ def test_invalid_arguments_return_codes_without_gpu(lib):
     assert lib.gcge_spmm(None, None, 0, 0, None, 0, None) == _lib.GCGE_ERR_INVALID_ARG
     lib.gcge_destroy(None)
     amg = ctypes.c_void_p()
-    assert lib.gcge_amg_create(None, 10, 512, None, ctypes.byref(amg)) == _lib.GCGE_ERR_INVALID_ARG
+    assert lib.gcge_amg_create(None, 10, 512, 0.02, None, ctypes.byref(amg)) == _lib.GCGE_ERR_INVALID_ARG
     assert not amg.value
     assert lib.gcge_amg_apply(None, None, 0, 1, None, 0, None) == _lib.GCGE_ERR_INVALID_ARG
     nl = ctypes.c_int(0)
