@@ -32,6 +32,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -116,9 +117,10 @@ double gershgorin(const HCsr &A, const std::vector<double> &d) {
     return rho;
 }
 
-// Rows of a sparse matrix built row by row in parallel: cnt pass, then fill.
+// Rows of a sparse matrix built row by row in parallel, chunk by chunk.
+// Returns false when the result has more entries than int32 row pointers hold.
 template <typename RowFn>
-void build_rows(int64_t n, int64_t m, HCsr &out, RowFn &&row) {
+bool build_rows(int64_t n, int64_t m, HCsr &out, RowFn &&row) {
     out.n = n;
     out.m = m;
     out.rp.assign(n + 1, 0);
@@ -151,6 +153,9 @@ void build_rows(int64_t n, int64_t m, HCsr &out, RowFn &&row) {
             }
         }
     }
+    int64_t total = 0;
+    for (int64_t c = 0; c < nch; ++c) total += (int64_t)cci[c].size();
+    if (total > INT32_MAX) return false;
     for (int64_t c = 0; c < nch; ++c)
         for (size_t t = 0; t < ccnt[c].size(); ++t) out.rp[c * CH + t + 1] = ccnt[c][t];
     for (int64_t i = 0; i < n; ++i) out.rp[i + 1] += out.rp[i];
@@ -161,18 +166,19 @@ void build_rows(int64_t n, int64_t m, HCsr &out, RowFn &&row) {
         std::copy(cci[c].begin(), cci[c].end(), out.ci.begin() + off);
         std::copy(cva[c].begin(), cva[c].end(), out.va.begin() + off);
     }
+    return true;
 }
 
 // P = (I - omega D^-1 A) P_t: row i holds the aggregates of the columns of
 // row i of A; entry a gets -omega/a_ii sum_{j in row i, agg(j) = a} a_ij t_a,
 // plus t_a at a = agg(i).
-void smoothed_p(const HCsr &A, const std::vector<double> &d, const std::vector<int32_t> &agg, int64_t nagg,
+bool smoothed_p(const HCsr &A, const std::vector<double> &d, const std::vector<int32_t> &agg, int64_t nagg,
                 double omega, HCsr &P) {
     std::vector<int64_t> cnt(nagg, 0);
     for (int32_t a : agg) ++cnt[a];
     std::vector<double> t(nagg);
     for (int64_t a = 0; a < nagg; ++a) t[a] = 1.0 / std::sqrt((double)cnt[a]);
-    build_rows(A.n, nagg, P,
+    return build_rows(A.n, nagg, P,
                [&](int64_t i, std::vector<std::pair<int32_t, double>> &buf, std::vector<double> &acc,
                    std::vector<int64_t> &mark) {
                    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
@@ -210,8 +216,8 @@ void transpose(const HCsr &P, HCsr &R) {
 }
 
 // C = A B (Gustavson, row by row; sums in the order of A's row and B's rows)
-void spgemm(const HCsr &A, const HCsr &B, HCsr &C) {
-    build_rows(A.n, B.m, C,
+bool spgemm(const HCsr &A, const HCsr &B, HCsr &C) {
+    return build_rows(A.n, B.m, C,
                [&](int64_t i, std::vector<std::pair<int32_t, double>> &buf, std::vector<double> &acc,
                    std::vector<int64_t> &mark) {
                    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
@@ -243,14 +249,16 @@ bool spd_inverse(const HCsr &A, std::vector<double> &inv) {
         if (!(s > 0.0)) return false;
         const double ljj = std::sqrt(s);
         L[(size_t)j * n + j] = ljj;
+#pragma omp parallel for schedule(static)
         for (int64_t i = j + 1; i < n; ++i) {
             double v = M[(size_t)i * n + j];
             for (int64_t p = 0; p < j; ++p) v -= L[(size_t)i * n + p] * L[(size_t)j * n + p];
             L[(size_t)i * n + j] = v / ljj;
         }
     }
-    // Linv (lower) by forward substitution, inv = Linv^T Linv
+    // Linv (lower) by forward substitution, column by column; inv = Linv^T Linv
     std::vector<double> Li((size_t)n * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 8)
     for (int64_t c = 0; c < n; ++c)
         for (int64_t i = c; i < n; ++i) {
             double v = (i == c) ? 1.0 : 0.0;
@@ -406,10 +414,14 @@ int Amg::build(const DevCsr<double> &A0, int max_levels, int coarse_max, double 
         L.w = (double *)pw;
         L.w32 = (float *)pw32;
         HCsr P, R, AP, Ac;
-        smoothed_p(cur, d, ag, nagg, om, P);
-        transpose(P, R);
-        spgemm(cur, P, AP);
-        spgemm(R, AP, Ac);
+        bool fits = smoothed_p(cur, d, ag, nagg, om, P);
+        if (fits) transpose(P, R);
+        fits = fits && spgemm(cur, P, AP) && spgemm(R, AP, Ac);
+        if (!fits) {
+            err = "amg: a product of level " + std::to_string(lev) + " exceeds 2^31 stored entries";
+            release();
+            return GCGE_ERR_INVALID_ARG;
+        }
         if (e == hipSuccess) e = upload_csr(owned, P, L.P);
         if (e == hipSuccess) e = upload_csr(owned, R, L.R);
         if (e == hipSuccess) e = upload_f32(owned, P, L.P, L.P32);
