@@ -1554,15 +1554,29 @@ __global__ __launch_bounds__(256) void k_gemm_rows(int64_t n, const double *__re
     __shared__ double Ss[32 * 32];
     for (int i = threadIdx.x; i < m * k; i += 256) Ss[i] = S[(int64_t)(i / k) * lds + i % k];
     __syncthreads();
-    constexpr int NGR = 256 / G;
+    constexpr int NGR = 256 / G, RU = 4;   // RU rows per group and step: RU loads in flight per lane
     const int grp = threadIdx.x / G, l = threadIdx.x % G;
     const int lx = l < m ? l : 0, ly = l < k ? l : 0;   // clamped columns: loads carry no branch
-    for (int64_t row = (int64_t)blockIdx.x * NGR + grp; row < n; row += (int64_t)gridDim.x * NGR) {
-        const double xv = X[row * ldx + lx];
-        const double yo = (beta != 0.0) ? Y[row * ldy + ly] : 0.0;
-        double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc = fma(__shfl(xv, j, G), Ss[j * k + ly], acc);
-        if (l < k) Y[row * ldy + l] = (beta != 0.0) ? fma(beta, yo, alpha * acc) : alpha * acc;
+    for (int64_t rb = ((int64_t)blockIdx.x * NGR + grp) * RU; rb < n; rb += (int64_t)gridDim.x * NGR * RU) {
+        // every row of the step is read before any is written (Y may be X):
+        // rows past n read row n - 1 and are not stored
+        double xv[RU], yo[RU], acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t rc = min(rb + u, n - 1);
+            xv[u] = X[rc * ldx + lx];
+            yo[u] = (beta != 0.0) ? Y[rc * ldy + ly] : 0.0;
+            acc[u] = 0.0;
+        }
+        for (int j = 0; j < m; ++j) {
+            const double sv = Ss[j * k + ly];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) acc[u] = fma(__shfl(xv[u], j, G), sv, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (l < k && rb + u < n)
+                Y[(rb + u) * ldy + l] = (beta != 0.0) ? fma(beta, yo[u], alpha * acc[u]) : alpha * acc[u];
     }
 }
 
@@ -1572,7 +1586,8 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
     if (X.nseg == 1 && X.s[0].ncol <= 32 && k <= 32) {
         const int m = X.s[0].ncol, w = std::max(m, k);
         const int G = w <= 8 ? 8 : w <= 16 ? 16 : 32;
-        const int64_t nb = std::min<int64_t>((n + 256 / G - 1) / (256 / G), (int64_t)num_cu() * 16);
+        const int64_t rows_per_wg = 256 / G * 4;
+        const int64_t nb = std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, (int64_t)num_cu() * 16);
 #define GCGE_GR(Gv)                                                                                          \
     if (G == Gv) hipLaunchKernelGGL(k_gemm_rows<Gv>, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, \
                                     S, lds, k, alpha, beta, Y, ldy);
