@@ -262,3 +262,19 @@ def test_solver_multigrid_mixed_precision_matches_fp64(g):
         lam, X, st = s.solve()
     np.testing.assert_allclose(lam, ref, rtol=1e-10)
     assert st["max_rel_residual"] <= 1e-8
+
+
+def test_solver_rebuilds_the_hierarchy_after_new_values(g):
+    # gcge_update_values with A scaled by 2: the preconditioned solve must use
+    # a hierarchy of the new operator (eigenvalues double, residuals at tol).
+    A = wl.laplace3d_7pt(10)
+    d = wl.diag_uniform(A.n)
+    ref = orc.pencil_eigs(A, "diag", d, 14)[0][:8]
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, dev(d), 8, 1e-8, block_size=4, precond=1, amg_coarse=64) as s:
+        lam1, _, st1 = s.solve()
+        s.update_values(2.0 * Ad.val)
+        lam2, _, st2 = s.solve()
+    np.testing.assert_allclose(lam1, ref, rtol=1e-10)
+    np.testing.assert_allclose(lam2, 2.0 * ref, rtol=1e-10)
+    assert st2["max_rel_residual"] <= 1e-8
