@@ -264,7 +264,8 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                                                const int *__restrict__ skip, const int32_t *__restrict__ uorder,
                                                Affine<T> af) {
     if (skip != nullptr && skip[0] == 0) return;
-    constexpr int NG = 256 / G, U = 8;
+    // batches of 7 nonzeros: one batch per row of a 7-point stencil, four per 27-point row
+    constexpr int NG = 256 / G, U = 7;
     constexpr int RS = NG > 32 ? NG : 32;   // rows per staged block (divides 64)
     constexpr int RPG = RS / NG;            // rows per group per block
     constexpr int CAP = 1024;               // staged nonzeros per block
@@ -305,9 +306,10 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
             if (lr >= nrows) break;
             const int64_t row = base + lr;
             const int e0 = s_rp[lr] - eb, e1 = s_rp[lr + 1] - eb;
-            Vec<T, V> acc, accb;
+            Vec<T, V> acc, accb, xself;   // xself: the gathered own row (FP32 RED 2, below)
+            bool found = false;
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc.v[v] = accb.v[v] = T(0);
+            for (int v = 0; v < V; ++v) acc.v[v] = accb.v[v] = xself.v[v] = T(0);
             // Slots past the row end re-read the row's last entry (a valid
             // address) with a zero weight, and lanes past column k read column
             // 0: every load is unconditional, so the eight gathers of a batch
@@ -349,6 +351,16 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                 Vec<T, V> xv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) xv[u] = vld<T, V>(X + (int64_t)cc[u] * ldx + c0l);
+                if (RED == 2 && sizeof(T) == 4) {
+                    // the dot q . p of the CG needs p's own row, which the
+                    // diagonal entry has just gathered (saves a load in FP32)
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (cc[u] == (int)row) {
+                            xself = xv[u];
+                            found = true;
+                        }
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -400,7 +412,8 @@ __global__ __launch_bounds__(256) void k_spmms(int64_t n, const int32_t *__restr
                         red2[v] = fma(bx[v], bx[v], red2[v]);
                     }
             } else if (RED == 2) {
-                const Vec<T, V> z = vld<T, V>(Z + row * ldz + c0);
+                Vec<T, V> z = xself;
+                if (!(sizeof(T) == 4 && found && Z == X && ldz == ldx)) z = vld<T, V>(Z + row * ldz + c0);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (c0 + v < k) red1[v] = fma(acc.v[v], z.v[v], red1[v]);
