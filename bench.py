@@ -163,9 +163,17 @@ def short_name(kernel_name):
 
 
 def kernel_source_hash():
+    """SHA-256 of the kernel source with comments and blank lines removed, so
+    that counters stay attached to the code they were taken on, not to its
+    comments."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    import re
+    with open(KERNEL_SOURCE) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    code = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def summarize_trace(d, top=30):

@@ -248,7 +248,7 @@ __device__ __forceinline__ void vst_nt(T *p, const Vec<T, V> &x) {
 // one dependent global round trip per row instead of three).  Blocks whose
 // nonzeros do not fit the staging area fall back to global index loads.
 // 16-byte vector accesses: a group of G lanes per row, lane l owns columns
-// V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 8, all eight
+// V*l .. V*l+V-1; the nonzeros of a row are taken in batches of 7, all seven
 // gathered vector rows being requested before they are used.  Requires
 // 16-byte aligned rows and leading dimensions that cover round_up(k, V)
 // columns: the tail lane reads padding columns of the inputs (never part of a
