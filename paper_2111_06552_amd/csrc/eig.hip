@@ -48,6 +48,8 @@ __device__ __forceinline__ double wmax(double v) {
 }
 
 // Sum over a work-group of NW waves, identical in every thread, fixed order.
+// No barrier after the read of red: the caller must not write red again
+// before a later barrier (the tridiagonalization alternates two buffers).
 template <int NW>
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -57,7 +59,6 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     double t = 0.0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) t += red[i];
-    __syncthreads();
     return t;
 }
 
@@ -79,23 +80,30 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 constexpr int TRI_T = 1024, TRI_W = TRI_T / 64;
 static_assert(DENSE_EIG_MAX <= 12 * 64, "k_tridiag instances cover 12 column slots per lane");
 
+// Rows of the LDS buffer that combines the per-wave column sums: 8 (two
+// stages) while (6 + 8) n doubles fit in 64 KiB, else 4 (four stages).
+__host__ __device__ constexpr int tri_comb_rows(int ns) { return ns <= 8 ? 8 : 4; }
+
 // y = C v over the trailing block C = rows/cols r0..n-1, first applying the
 // pending update C -= sv sw^T + sw sv^T when UPD.  y goes to sy[r0..n-1].
-// A wave takes four consecutive rows at a time (all their loads in flight
-// together); lane l holds columns l, l + 64, ... (NS slots).
-template <bool UPD, int NS>
+// A wave takes RU consecutive rows at a time; lane l holds columns l, l + 64,
+// ... (NS slots).  The loads of a row group are issued SB slots at a time
+// before any of them is used (clamped in-bounds addresses, values masked
+// afterwards), so the group pays one memory latency per SB slots; slots wholly
+// right of the group's last row are skipped (a wave-uniform test).
+template <bool UPD, int NS, int RU, int SB, int CR>
 __device__ __forceinline__ void tri_pass(int n, double *__restrict__ a, int64_t lda, int r0,
                                          const double *sv, const double *sw, const double *vn, double *sy,
                                          double *comb) {
-    constexpr int RU = 2;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int mm = n - r0;
     double part[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) part[t] = 0.0;
     for (int rb = wave * RU; rb < mm; rb += TRI_W * RU) {
+        const int nsl = min(rb + RU - 1, mm - 1) / 64 + 1;   // slots holding columns <= the last row
         double acc[RU], vi[RU], wi[RU], vni[RU];
-        const double *rows[RU];
+        double *rows[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int i = min(r0 + rb + u, n - 1);
@@ -105,25 +113,43 @@ __device__ __forceinline__ void tri_pass(int n, double *__restrict__ a, int64_t 
             vni[u] = vn[i];
             rows[u] = a + (int64_t)i * lda + r0;
         }
+        // slots in batches of SB: the loads of a batch are all in flight together
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            const int r = lane + 64 * t;
-            const int rc = min(r, mm - 1);
-            double x[RU];
+        for (int t0 = 0; t0 < NS; t0 += SB) {
+            if (t0 < nsl) {
+                double x[SB][RU];
 #pragma unroll
-            for (int u = 0; u < RU; ++u) x[u] = (rb + u < mm && r <= rb + u) ? rows[u][rc] : 0.0;
-            const double swr = UPD ? sw[r0 + rc] : 0.0, svr = UPD ? sv[r0 + rc] : 0.0, vnr = vn[r0 + rc];
+                for (int b = 0; b < SB; ++b) {
+                    const int t = t0 + b;
+                    if (t < NS && t < nsl) {
+                        const int rc = min(lane + 64 * t, mm - 1);
 #pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int ri = rb + u;
-                if (ri < mm && r <= ri) {
-                    double xv = x[u];
-                    if (UPD) {
-                        xv -= vi[u] * swr + wi[u] * svr;
-                        const_cast<double *>(rows[u])[r] = xv;
+                        for (int u = 0; u < RU; ++u) x[b][u] = rows[u][rc];
                     }
-                    acc[u] += xv * vnr;
-                    if (r < ri) part[t] += xv * vni[u];
+                }
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                    const int t = t0 + b;
+                    if (t < NS && t < nsl) {
+                        const int r = lane + 64 * t;
+                        const int rc = min(r, mm - 1);
+                        const double swr = UPD ? sw[r0 + rc] : 0.0, svr = UPD ? sv[r0 + rc] : 0.0;
+                        const double vnr = vn[r0 + rc];
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) {
+                            const int ri = rb + u;
+                            const bool in = ri < mm && r <= ri;
+                            double xv = x[b][u];
+                            if (UPD) {
+                                xv -= vi[u] * swr + wi[u] * svr;
+                                if (in) rows[u][r] = xv;
+                            }
+                            xv = in ? xv : 0.0;
+                            acc[u] += xv * vnr;
+                            const double xp = r < ri ? xv : 0.0;
+                            part[t] += xp * vni[u];
+                        }
+                    }
                 }
             }
         }
@@ -133,15 +159,18 @@ __device__ __forceinline__ void tri_pass(int n, double *__restrict__ a, int64_t 
             if (lane == 0 && rb + u < mm) sy[r0 + rb + u] = s;
         }
     }
-    __syncthreads();
-    // column contributions: comb[q] = part of wave q + 12, + wave q + 8, + wave q + 4, + wave q
-    for (int stage = 3; stage >= 0; --stage) {
-        if (wave / 4 == stage) {
-            double *c = comb + (int64_t)(wave % 4) * n;
+    // column contributions, combined in a fixed order: comb[q] = part of wave
+    // q + CR (NST - 1), + ..., + wave q; y = sy + comb[0] + ... + comb[CR - 1].
+    // (comb was last read before the barrier that ended the previous pass, and
+    // sy is read only after the stage barriers.)
+    constexpr int NST = TRI_W / CR;
+    for (int stage = NST - 1; stage >= 0; --stage) {
+        if (wave / CR == stage) {
+            double *c = comb + (int64_t)(wave % CR) * n;
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
                 const int r = lane + 64 * t;
-                if (r < mm) c[r] = (stage == 3) ? part[t] : c[r] + part[t];
+                if (r < mm) c[r] = (stage == NST - 1) ? part[t] : c[r] + part[t];
             }
         }
         __syncthreads();
@@ -149,20 +178,20 @@ __device__ __forceinline__ void tri_pass(int n, double *__restrict__ a, int64_t 
     for (int r = tid; r < mm; r += TRI_T) {
         double y = sy[r0 + r];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y += comb[(int64_t)q * n + r];
+        for (int q = 0; q < CR; ++q) y += comb[(int64_t)q * n + r];
         sy[r0 + r] = y;
     }
     __syncthreads();
 }
 
 // Reflector from x[r0..n-1] (x[r0] = alpha): v -> sv2[r0..n-1], returns
-// (tau, beta).  Identical in every thread.
+// (tau, beta).  Identical in every thread.  sq is this thread's share of
+// sum x[i]^2 over i > r0, accumulated while x was written (the barrier in the
+// block sum publishes x).
 __device__ __forceinline__ void tri_reflector(int n, int r0, const double *x, double *sv2, double *red,
-                                              double &tau_out, double &beta_out) {
+                                              double sq, double &tau_out, double &beta_out) {
     const int tid = threadIdx.x;
-    double s = 0.0;
-    for (int i = r0 + 1 + tid; i < n; i += TRI_T) s += x[i] * x[i];
-    s = block_sum<TRI_W>(s, red);
+    const double s = block_sum<TRI_W>(sq, red);
     const double alpha = x[r0];
     if (s == 0.0) {
         for (int i = r0 + tid; i < n; i += TRI_T) sv2[i] = (i == r0) ? 1.0 : 0.0;
@@ -190,14 +219,15 @@ __device__ __forceinline__ void tri_w(int n, int r0, double t, const double *sy,
     __syncthreads();
 }
 
-template <int NS>
+template <int NS, int RU, int SB>
 __global__ __launch_bounds__(TRI_T) void k_tridiag(int n, double *__restrict__ a, int64_t lda,
                                                     double *__restrict__ d, double *__restrict__ e,
                                                     double *__restrict__ tau) {
     extern __shared__ double sm[];
     double *svA = sm, *swA = sm + n, *svB = sm + 2 * n, *swB = sm + 3 * n, *sy = sm + 4 * n, *sx = sm + 5 * n;
-    double *comb = sm + 6 * n;   // 4 x n
-    __shared__ double red[TRI_W];
+    constexpr int CR = tri_comb_rows(NS);
+    double *comb = sm + 6 * n;   // CR x n
+    __shared__ double red[2][TRI_W];   // block sums: reflector norms, then p.v
     const int tid = threadIdx.x;
     if (n <= 2) {
         if (tid == 0) {
@@ -211,35 +241,42 @@ __global__ __launch_bounds__(TRI_T) void k_tridiag(int n, double *__restrict__ a
         return;
     }
     // reflector 0 from row 0 (the input is fully symmetric)
-    for (int i = 1 + tid; i < n; i += TRI_T) sx[i] = a[i];
-    __syncthreads();
+    double sq = 0.0;
+    for (int i = 1 + tid; i < n; i += TRI_T) {
+        const double v = a[i];
+        sx[i] = v;
+        sq += i >= 2 ? v * v : 0.0;
+    }
     double t0, b0;
-    tri_reflector(n, 1, sx, svA, red, t0, b0);
+    tri_reflector(n, 1, sx, svA, red[0], sq, t0, b0);
     for (int i = 1 + tid; i < n; i += TRI_T) a[i] = svA[i];
     if (tid == 0) {
         d[0] = a[0];
         e[0] = b0;
         tau[0] = t0;
     }
-    tri_pass<false, NS>(n, a, lda, 1, nullptr, nullptr, svA, sy, comb);
-    tri_w(n, 1, t0, sy, svA, swA, red);
+    tri_pass<false, NS, RU, SB, CR>(n, a, lda, 1, nullptr, nullptr, svA, sy, comb);
+    tri_w(n, 1, t0, sy, svA, swA, red[1]);
     double *sv = svA, *sw = swA, *sv2 = svB, *sw2 = swB;
     for (int k = 0; k + 4 <= n; ++k) {
         const int k1 = k + 1;
         // updated column k1 below the diagonal and the diagonal entry
-        for (int i = k1 + 1 + tid; i < n; i += TRI_T)
-            sx[i] = a[(int64_t)i * lda + k1] - (sv[i] * sw[k1] + sw[i] * sv[k1]);
+        double sq1 = 0.0;
+        for (int i = k1 + 1 + tid; i < n; i += TRI_T) {
+            const double v = a[(int64_t)i * lda + k1] - (sv[i] * sw[k1] + sw[i] * sv[k1]);
+            sx[i] = v;
+            sq1 += i >= k1 + 2 ? v * v : 0.0;
+        }
         if (tid == 0) d[k1] = a[(int64_t)k1 * lda + k1] - (sv[k1] * sw[k1] + sw[k1] * sv[k1]);
-        __syncthreads();
         double t1, b1;
-        tri_reflector(n, k1 + 1, sx, sv2, red, t1, b1);
+        tri_reflector(n, k1 + 1, sx, sv2, red[0], sq1, t1, b1);
         for (int i = k1 + 1 + tid; i < n; i += TRI_T) a[(int64_t)k1 * lda + i] = sv2[i];
         if (tid == 0) {
             e[k1] = b1;
             tau[k1] = t1;
         }
-        tri_pass<true, NS>(n, a, lda, k1 + 1, sv, sw, sv2, sy, comb);
-        tri_w(n, k1 + 1, t1, sy, sv2, sw2, red);
+        tri_pass<true, NS, RU, SB, CR>(n, a, lda, k1 + 1, sv, sw, sv2, sy, comb);
+        tri_w(n, k1 + 1, t1, sy, sv2, sw2, red[1]);
         double *tv = sv, *tw = sw;
         sv = sv2;
         sw = sw2;
@@ -542,11 +579,16 @@ hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, 
     if (e != hipSuccess) return e;
     {
         const int ns = (n + 63) / 64;   // column slots per lane
-        const size_t lds = sizeof(double) * 10 * n;
-#define GCGE_TRI(NSv) \
-    if (ns == NSv) hipLaunchKernelGGL((k_tridiag<NSv>), dim3(1), dim3(TRI_T), lds, st, n, a, (int64_t)n, dg, off, tau);
-        GCGE_TRI(1) GCGE_TRI(2) GCGE_TRI(3) GCGE_TRI(4) GCGE_TRI(5) GCGE_TRI(6)
-        GCGE_TRI(7) GCGE_TRI(8) GCGE_TRI(9) GCGE_TRI(10) GCGE_TRI(11) GCGE_TRI(12)
+        const size_t lds = sizeof(double) * (6 + tri_comb_rows(ns)) * n;
+        // rows per group and slots per load batch, the fastest measured at
+        // n = 300..500 (one row per group from 5 slots on; two rows would run
+        // out of registers from 7 on)
+#define GCGE_TRI(NSv, RUv, SBv)                                                                   \
+    if (ns == NSv)                                                                                 \
+        hipLaunchKernelGGL((k_tridiag<NSv, RUv, SBv>), dim3(1), dim3(TRI_T), lds, st, n, a, (int64_t)n, dg, off, tau);
+        GCGE_TRI(1, 2, 4) GCGE_TRI(2, 2, 4) GCGE_TRI(3, 2, 4) GCGE_TRI(4, 2, 4) GCGE_TRI(5, 1, 4)
+        GCGE_TRI(6, 1, 4) GCGE_TRI(7, 1, 4) GCGE_TRI(8, 1, 4) GCGE_TRI(9, 1, 2) GCGE_TRI(10, 1, 2)
+        GCGE_TRI(11, 1, 2) GCGE_TRI(12, 1, 2)
 #undef GCGE_TRI
     }
     hipLaunchKernelGGL(k_bisect, dim3(nwant), dim3(64), sizeof(double) * 2 * n, st, n, dg, off, nwant, w);
