@@ -1146,11 +1146,15 @@ GCGE_CG_INST(float)
 // ---------------------------------------------------------------------------
 // Block inner product C = X^T diag(d) Y on the FP64 matrix cores.
 // A work-group (4 waves) owns one (TM x TN) output tile over one chunk of
-// rows; each wave streams every 4th group of 4 rows and feeds them straight
-// from global memory into v_mfma_f64_16x16x4f64 (the 16 consecutive columns
-// of a row that one MFMA operand needs are one 128-byte load).  The four
-// waves' tiles are summed in LDS in a fixed order and written as one partial;
-// a second kernel sums the partials over the chunks.
+// rows; each wave streams every 4th group of 4 NS rows (NS = 1 for 16 x 16
+// tiles, 2 for 32 x 32: the fastest measured) and feeds them straight from
+// global memory into v_mfma_f64_16x16x4f64 (the 16 consecutive columns of a
+// row that one MFMA operand needs are one 128-byte load).  The loads of the
+// next group are in flight while the current one is consumed (NS MFMA
+// steps), with clamped addresses and masked values.  When the Y tile is the X
+// strip itself (X^T D X), Y is not loaded again.  The four waves' tiles are
+// summed in LDS in a fixed order and written as one partial; a second kernel
+// sums the partials over the chunks.
 // ---------------------------------------------------------------------------
 struct GTile {
     const double *xp;
@@ -1174,7 +1178,7 @@ struct GramParams {
     int64_t rows_per;
 };
 
-template <int MB, int NB>
+template <int MB, int NB, int NS = MB == 1 ? 1 : 2>   // NS MFMA steps (4 rows each) per group
 __global__ __launch_bounds__(256) void k_gram(GramParams P) {
     constexpr int TM = 16 * MB, TN = 16 * NB;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -1193,40 +1197,61 @@ __global__ __launch_bounds__(256) void k_gram(GramParams P) {
     bool xv[MB], yv[NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
-        xc[a] = tl.xcol0 + a * 16 + li;
         xv[a] = (a * 16 + li) < tl.ncol;
+        xc[a] = xv[a] ? tl.xcol0 + a * 16 + li : 0;   // clamped: loads carry no branch
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        yc[b] = yt * TN + b * 16 + li;
-        yv[b] = yc[b] < P.k;
+        yv[b] = yt * TN + b * 16 + li < P.k;
+        yc[b] = yv[b] ? yt * TN + b * 16 + li : 0;
     }
-    // operands of the next group of rows are requested before the MFMAs of
-    // the current group (register double buffering)
-    double av[MB], bv[NB], an[MB], bn[NB];
-    auto load = [&](int64_t rb, double *ao, double *bo) {
-        const int64_t row = rb + lk;
-        const bool rv = row < r1;
-        const double *xr = tl.xp + row * tl.ldx;
-        const double *yr = P.Y + row * P.ldy;
-        const double dw = (P.d != nullptr && rv) ? P.d[row] : 1.0;
+    // Y is the X strip itself: same address, stride and valid columns
+    const bool same = MB == NB && tl.xp + tl.xcol0 == P.Y + yt * TN && tl.ldx == P.ldy &&
+                      tl.ncol == min(TN, P.k - yt * TN);
+    double av[NS][MB], bv[NS][NB], an[NS][MB], bn[NS][NB];
+    auto load = [&](int64_t rb, double (&ao)[NS][MB], double (&bo)[NS][NB]) {
+        double xr[NS][MB], yr[NS][NB], dw[NS];
 #pragma unroll
-        for (int a = 0; a < MB; ++a) ao[a] = (rv && xv[a]) ? xr[xc[a]] : 0.0;
+        for (int q = 0; q < NS; ++q) {
+            const int64_t row = min(rb + 4 * q + lk, r1 - 1);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bo[b] = (rv && yv[b]) ? yr[yc[b]] * dw : 0.0;
+            for (int a = 0; a < MB; ++a) xr[q][a] = tl.xp[row * tl.ldx + xc[a]];
+            if (!same) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) yr[q][b] = P.Y[row * P.ldy + yc[b]];
+            }
+            dw[q] = P.d != nullptr ? P.d[row] : 1.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const bool rv = rb + 4 * q + lk < r1;
+#pragma unroll
+            for (int a = 0; a < MB; ++a) ao[q][a] = (rv && xv[a]) ? xr[q][a] : 0.0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const double y = same ? xr[q][b < MB ? b : 0] : yr[q][b];
+                bo[q][b] = (rv && yv[b]) ? y * dw[q] : 0.0;
+            }
+        }
     };
-    int64_t rb = r0 + wave * 4;
+    int64_t rb = r0 + wave * 4 * NS;
     load(rb, av, bv);
-    for (; rb < r1; rb += 16) {
-        load(rb + 16, an, bn);
+    for (; rb < r1; rb += 16 * NS) {
+        load(rb + 16 * NS, an, bn);   // past the chunk end: clamped addresses, masked to zero
 #pragma unroll
-        for (int a = 0; a < MB; ++a)
+        for (int q = 0; q < NS; ++q)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int a = 0; a < MB; ++a) av[a] = an[a];
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][a], bv[q][b], acc[a][b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = bn[b];
+        for (int q = 0; q < NS; ++q) {
+#pragma unroll
+            for (int a = 0; a < MB; ++a) av[q][a] = an[q][a];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bv[q][b] = bn[q][b];
+        }
     }
     __shared__ double sh[TM * TN];
     for (int w = 0; w < 4; ++w) {
@@ -1593,6 +1618,72 @@ __global__ __launch_bounds__(256) void k_gemm_rows(int64_t n, const double *__re
     }
 }
 
+// Narrow products with at most 16 input and 16 output columns (the leaves of
+// Algorithm 3): a row per 16-lane DPP row.  Lane l holds X[row][l] and column
+// l of S in registers (rows of S past m are zero), and X[row][j] reaches every
+// lane of the row by a DPP row broadcast (a VALU move, no LDS).  The next rows
+// are loaded before the current ones are combined and stored; rows belong to
+// one group, so Y may alias X.
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + J, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + J, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// acc[u] += sum over j = J..15 of X[row u][j] S[j][l], j in order.  The
+// empty asm makes the next broadcast of each row wait for its FMA, so that at
+// most RU broadcasts are live (the compiler would otherwise hoist all of them).
+template <int J, int RU>
+__device__ __forceinline__ void row_bcast_fma(double (&xv)[RU], const double (&sv)[16], double (&acc)[RU]) {
+    if constexpr (J < 16) {
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            acc[u] = fma(row_bcast<J>(xv[u]), sv[J], acc[u]);
+            asm volatile("" : "+v"(xv[u]) : "v"(acc[u]));
+        }
+        row_bcast_fma<J + 1, RU>(xv, sv, acc);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_rows16(int64_t n, const double *__restrict__ X, int64_t ldx, int m,
+                                                     const double *__restrict__ S, int64_t lds, int k, double alpha,
+                                                     double beta, double *Y, int64_t ldy) {
+    constexpr int NGR = 16, RU = 4;   // 16 row groups of 16 lanes; RU rows per group and step
+    const int grp = threadIdx.x / 16, l = threadIdx.x % 16;
+    const int lx = l < m ? l : 0, ly = l < k ? l : 0;   // clamped columns: loads carry no branch
+    double sv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sv[j] = (j < m && l < k) ? S[(int64_t)j * lds + l] : 0.0;
+    const int64_t step = (int64_t)gridDim.x * NGR * RU;
+    double xn[RU], yn[RU];
+    auto load = [&](int64_t rb) {   // rows past n read row n - 1 and are not stored
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t rc = min(rb + u, n - 1);
+            xn[u] = X[rc * ldx + lx];
+            yn[u] = (beta != 0.0) ? Y[rc * ldy + ly] : 0.0;
+        }
+    };
+    int64_t rb = ((int64_t)blockIdx.x * NGR + grp) * RU;
+    if (rb < n) load(rb);
+    for (; rb < n; rb += step) {
+        double xv[RU], yo[RU], acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            xv[u] = xn[u];
+            yo[u] = yn[u];
+            acc[u] = 0.0;
+        }
+        if (rb + step < n) load(rb + step);
+        row_bcast_fma<0, RU>(xv, sv, acc);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (l < k && rb + u < n)
+                Y[(rb + u) * ldy + l] = (beta != 0.0) ? fma(beta, yo[u], alpha * acc[u]) : alpha * acc[u];
+    }
+}
+
 hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
                 double *Y, int64_t ldy, hipStream_t st) {
     if (n == 0 || k == 0) return hipSuccess;
@@ -1601,10 +1692,13 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
         const int G = w <= 8 ? 8 : w <= 16 ? 16 : 32;
         const int64_t rows_per_wg = 256 / G * 4;
         const int64_t nb = std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, (int64_t)num_cu() * 16);
+        if (G == 16)
+            hipLaunchKernelGGL(k_gemm_rows16, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, S, lds,
+                               k, alpha, beta, Y, ldy);
 #define GCGE_GR(Gv)                                                                                          \
     if (G == Gv) hipLaunchKernelGGL(k_gemm_rows<Gv>, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, \
                                     S, lds, k, alpha, beta, Y, ldy);
-        GCGE_GR(8) GCGE_GR(16) GCGE_GR(32)
+        GCGE_GR(8) GCGE_GR(32)
 #undef GCGE_GR
         return hipGetLastError();
     }

@@ -288,8 +288,15 @@ def test_gradient_csr_B_reduced_grid(g):
             for e in wl.fd_sample(M, count=4, seed=57):
                 r, c, t = transposed_entry(M, int(e))
                 # step relative to the matrix's largest entry (entries range over
-                # orders of magnitude, some are stored zeros)
-                h = 1e-6 * np.max(np.abs(M.val))
+                # orders of magnitude, some are stored zeros).  A central
+                # difference errs by O(h^2) (truncation) plus O(delta f / h),
+                # where delta f ~ 1e-14 |f| is the rounding noise between two
+                # warm-started solves.  For A (entries ~1.8, gradients ~0.1) a
+                # relative step of 1e-6 keeps both well inside the tolerance
+                # (1e-4 already shows a truncation error of 1.3e-5 relative); for
+                # the mass matrix (entries ~6e-4, gradients ~100) 1e-6 puts the
+                # noise term at the tolerance, 1e-5 at about a third of it.
+                h = (1e-6 if which == "A" else 1e-5) * np.max(np.abs(M.val))
                 f = []
                 for sgn in (1.0, -1.0):
                     v = vals.clone()

@@ -124,8 +124,23 @@ def test_gram(g, n, m, k):
     assert np.array_equal(C1, C2)   # fixed summation order
 
 
+@pytest.mark.parametrize("n,m", [(1, 1), (1000, 16), (4099, 13), (3001, 32), (777, 7), (20000, 20)])
+def test_gram_self(g, n, m):
+    """X^T D X with Y the very same device buffer (the Algorithm 3 leaf Gram,
+    where the kernel does not load Y separately)."""
+    X = RNG.standard_normal((n, m))
+    d = RNG.uniform(0.5, 1.5, n)
+    Xd = dev(X)
+    for dd in (None, d):
+        C = g.gram(Xd, Xd, None if dd is None else dev(dd))
+        ref = orc.gram(X, X, dd)
+        bound = orc.gram(np.abs(X), np.abs(X), dd)
+        assert np.all(np.abs(C - ref) <= 1e-13 * bound + 1e-300)
+
+
 @pytest.mark.parametrize("n,m,k", [(1, 1, 1), (63, 5, 3), (1000, 16, 16), (5001, 25, 32), (2049, 32, 7),
-                                   (100, 3, 32), (4099, 50, 50), (5000, 450, 350), (777, 100, 130)])
+                                   (100, 3, 32), (4099, 50, 50), (5000, 450, 350), (777, 100, 130),
+                                   (1, 16, 9), (130, 12, 16), (65537, 13, 12), (64, 9, 1)])
 def test_gemm_update(g, n, m, k):
     X = RNG.standard_normal((n, m))
     S = RNG.standard_normal((m, k))
@@ -136,7 +151,7 @@ def test_gemm_update(g, n, m, k):
     assert np.all(np.abs(host(Y) - ref) <= 1e-13 * bound)
 
 
-@pytest.mark.parametrize("s0,k,kout", [(0, 16, 12), (3, 25, 25), (7, 9, 16), (1, 60, 50)])
+@pytest.mark.parametrize("s0,k,kout", [(0, 16, 12), (3, 25, 25), (7, 9, 16), (1, 60, 50), (2, 13, 13)])
 def test_gemm_in_place_row_transform(g, s0, k, kout):
     """Y aliases X (the in-place updates of Algorithm 3), columns starting at
     an odd offset of a wider block."""
