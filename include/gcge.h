@@ -129,6 +129,11 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "orth"         [3]     STEP 2 orthogonalization: 3 RecursiveOrthSVD (Algorithm 3), 2 modified
  *                         block orthogonalization (Algorithm 2, gcge_orth_mbo)
  *  "orth_block"   [0]     block size of Algorithm 2 (0: min(m/4, 200), Section 3.1)
+ *  "orth_skip_final" [0]  1: in Algorithm 3 and the deflation of W against [X, P], a pass
+ *                         loop stops at the first pass whose R (or Lambda - I) meets
+ *                         orth_tol without applying that pass's update (Algorithm 3 as
+ *                         printed applies it); the basis then meets the orth_tol test
+ *                         itself, one product fewer per loop
  *  "dense_eig"    [1]     small Rayleigh-Ritz eigenproblem on the device (gcge_dense_eig)
  *                         when its order is at most 768; 0 solves it on the host
  *                         (gcge_small_eigh)

@@ -297,7 +297,7 @@ def cg_columnwise(A, bkind, B, theta, R, maxit=30, rel_tol=1e-2, x0=None):
 # STEP 2: B-orthogonalization
 # ---------------------------------------------------------------------------
 
-def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8):
+def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8, skip_final=False):
     """Remove from W its B-components along the B-orthonormal block Q:
     repeat R = Q^T B W, W <- W - Q R until max|R| <= tol (at most max_pass
     passes).  This is the top split of the recursive orthogonalization, where
@@ -307,7 +307,11 @@ def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8):
     The columns of W are first scaled to unit B-norm.  A column whose squared
     B-norm falls to drop_tol or below in the first pass lay in span(Q): it is
     linearly dependent and dropped (later columns move forward); the others are
-    rescaled to unit B-norm.  Returns (W_out, passes)."""
+    rescaled to unit B-norm.  Returns (W_out, passes).
+
+    skip_final (an option, not the paper's listing): from the second pass on,
+    stop as soon as max|R| <= tol without applying that pass's update; W then
+    meets the stopping test itself.  passes counts the applied updates."""
     W = np.array(W, dtype=np.float64)
     passes = 0
     if Q.shape[1] == 0 or W.shape[1] == 0:
@@ -316,6 +320,8 @@ def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8):
     W = W[:, nrm > 0] / nrm[nrm > 0][None, :]
     for p in range(max_pass):
         Rm = b_gram(bkind, B, Q, W)
+        if skip_final and p > 0 and np.max(np.abs(Rm)) <= tol:
+            break
         W = W - Q @ Rm
         passes += 1
         if p == 0:
@@ -330,7 +336,7 @@ def deflate(W, Q, bkind, B, tol=1e-13, max_pass=3, drop_tol=1e-8):
 
 
 def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_pass=3,
-                       drop_tol=1e-8, leaf_passes=None, int_passes=None, counters=None):
+                       drop_tol=1e-8, leaf_passes=None, int_passes=None, counters=None, skip_final=False):
     """RecursiveOrthSVD (Algorithm 3) of the columns of X in the B inner product.
 
     Columns [s, e) with e - s <= c are a leaf: repeat M = X^T B X, M = Q Lam Q^T,
@@ -348,6 +354,11 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     paper's count of global reductions).  ``counters['gram']`` counts Gram
     products (the global reductions of the distributed version).
 
+    skip_final (an option, not the paper's listing, which applies the update of
+    the last pass): a leaf pass whose Lam already meets leaf_tol with nothing
+    dropped, or a node pass whose R meets int_tol, ends its loop without
+    applying its update.  ``counters['update']`` counts applied updates.
+
     Returns (X_out, kept) with X_out of shape (n, kept).
     """
     X = np.array(X, dtype=np.float64)
@@ -355,6 +366,7 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     if counters is None:
         counters = {}
     counters.setdefault("gram", 0)
+    counters.setdefault("update", 0)
     if m == 0:
         return X, 0
     # "eigenvalues close to zero" is judged on the unit-normalized input:
@@ -379,7 +391,10 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
                 lam, Qm = jacobi_eigh(M)
                 keep = lam > drop_tol
                 kk = int(np.sum(keep))
+                if skip_final and leaf_passes is None and kk == k and np.max(np.abs(lam - 1.0)) <= leaf_tol:
+                    break
                 X[:, s:s + kk] = blk @ (Qm[:, keep] / np.sqrt(lam[keep])[None, :])
+                counters["update"] += 1
                 k = kk
                 npass += 1
                 if leaf_passes is not None:
@@ -398,7 +413,10 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
                 X2 = X[:, s2:e2]
                 Rm = apply_b(bkind, B, X1).T @ X2
                 counters["gram"] += 1
+                if skip_final and int_passes is None and np.max(np.abs(Rm)) <= int_tol:
+                    break
                 X[:, s2:e2] = X2 - X1 @ Rm
+                counters["update"] += 1
                 npass += 1
                 if int_passes is not None:
                     if npass >= int_passes:

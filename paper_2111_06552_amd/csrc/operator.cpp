@@ -568,6 +568,7 @@ struct OrthCtx {
                     const double isq = 1.0 / std::sqrt(lam[j]);
                     for (int i = 0; i < k; ++i) S[(size_t)i * kk + q] = Q[(size_t)i * k + j] * isq;
                 }
+                if (opt.skip_final && kk == k && dev <= opt.orth_tol) break;   // already orthonormal
                 if (os) os->dropped += k - kk;
                 if (kk > 0) {
                     rc = gemm_host(X, S, kk, 1.0, 0.0, W + s, ldw);
@@ -604,6 +605,7 @@ struct OrthCtx {
                 if (rc) return rc;
                 double rmax = 0.0;
                 for (double v : R) rmax = std::max(rmax, std::fabs(v));
+                if (opt.skip_final && rmax <= opt.orth_tol) break;
                 Segs W1;
                 W1.add(W + s, ldw, k1);
                 rc = gemm_host(W1, R, l2, -1.0, 1.0, W + s2, ldw);
@@ -649,6 +651,7 @@ int orth_block(int64_t n, const BOp &B, const Segs &Q, double *W, int64_t ldw, i
             if (rc) return rc;
             double rmax = 0.0;
             for (double v : R) rmax = std::max(rmax, std::fabs(v));
+            if (opt.skip_final && pass > 0 && rmax <= opt.orth_tol) break;
             rc = C.gemm_host(Q, R, kk, -1.0, 1.0, W, ldw);
             if (rc) return rc;
             rc = C.refresh_bw(0, kk);

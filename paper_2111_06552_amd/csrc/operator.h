@@ -87,6 +87,11 @@ struct OrthOptions {
     int max_pass = 3;
     int algorithm = 3;   // 3: RecursiveOrthSVD (Algorithm 3); 2: modified block orthogonalization (Algorithm 2)
     int mbo_block = 0;   // block size b of Algorithm 2 (0: min(m/4, 200))
+    // Algorithm 3 and the deflation against Q: stop a pass loop as soon as a
+    // pass's R (or Lambda - I) meets orth_tol, without applying that pass's
+    // update (the paper's listing applies it; the result then meets the
+    // stopping test itself rather than its square)
+    bool skip_final = false;
 };
 
 // B-orthonormalize the n x k block W (ld) against the B-orthonormal block Q

@@ -280,7 +280,7 @@ struct gcge_handle_s {
     int profile = 0;
     KProf prof;
     int dense_eig_opt = 1;
-    int orth_alg = 3, orth_block_opt = 0;
+    int orth_alg = 3, orth_block_opt = 0, orth_skip_final = 0;
     DenseEigWork eigw;
     double *rrbuf = nullptr;   // device: Abar, its eigenvalues and eigenvectors
     size_t rrcap = 0;
@@ -561,6 +561,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     oo.drop_tol = drop_tol;
     oo.algorithm = orth_alg;
     oo.mbo_block = orth_block_opt;
+    oo.skip_final = orth_skip_final != 0;
     OrthStats ostat;
 
     // ---------------- STEPs 1-3, first pass: random block, orthogonalize, Rayleigh-Ritz
@@ -897,6 +898,7 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "dense_eig") { if (v != 0 && v != 1) return bad(); h->dense_eig_opt = (int)v; }
     else if (k == "orth") { if (v != 2 && v != 3) return bad(); h->orth_alg = (int)v; }
     else if (k == "orth_block") { if (v < 0 || v > 100000) return bad(); h->orth_block_opt = (int)v; }
+    else if (k == "orth_skip_final") { if (v != 0 && v != 1) return bad(); h->orth_skip_final = (int)v; }
     else if (k == "precond") { if (v != 0 && v != 1) return bad(); h->precond = (int)v; }
     else if (k == "amg_levels") {
         if (v < 1 || v > AMG_MAX_LEVELS) return bad();

@@ -113,6 +113,24 @@ def test_reduced_grid_parity_algorithm2(g, name, make, nev, opts):
     compare_vectors(bkind, B, lam_o, X_o, X, nev)
 
 
+@pytest.mark.parametrize("name,make,nev,opts", [
+    ("lap3d_10_diagB_skipfinal", lambda: (wl.laplace3d_7pt(10), "diag", wl.diag_uniform(1000)), 20,
+     dict(block_size=5, orth_skip_final=1)),
+    ("q1fem_9_moving_skipfinal", lambda: (wl.q1_fem(9)[0], "csr", wl.q1_fem(9)[1]), 40,
+     dict(block_size=8, moving=1, orth_skip_final=1)),
+])
+def test_reduced_grid_parity_orth_skip_final(g, name, make, nev, opts):
+    """The solver with the option that ends Algorithm 3's pass loops before the
+    last (sub-tolerance) update: same eigenpairs as the oracle."""
+    A, bkind, B = make()
+    lam, X, st = gpu_solve(g, A, bkind, B, nev, **opts)
+    lam_o, X_o = orc.pencil_eigs(A, bkind, B, nev + 8)
+    assert np.max(np.abs(lam - lam_o[:nev]) / np.abs(lam_o[:nev])) < 1e-10
+    check_pairs(A, bkind, B, lam, X, 1e-8)
+    compare_vectors(bkind, B, lam_o, X_o, X, nev)
+    assert st["orth_error"] < 1e-11
+
+
 def test_deterministic(g):
     A = wl.laplace3d_7pt(12)
     d = wl.diag_uniform(A.n)

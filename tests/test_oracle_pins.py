@@ -308,6 +308,34 @@ def test_recursive_orth_invariants(m):
     assert np.max(np.abs(Wo @ (Wo.T @ (d[:, None] * W)) - W)) < 1e-12 * np.abs(W).max()
 
 
+@pytest.mark.parametrize("m", [16, 40, 50])
+def test_orth_skip_final_option(m):
+    """The skip-final option (not the paper's listing): the output meets the
+    stopping test itself (B-orthonormal to 1e-13 up to rounding), spans the same
+    space, keeps the same columns, and applies fewer updates than Algorithm 3 as
+    printed; the deflation keeps W B-orthogonal to Q at the same level."""
+    n = 300
+    d = RNG.random(n) + 0.5
+    W = RNG.standard_normal((n, m))
+    W[:, 3] = W[:, 1] - W[:, 0]               # dependent: dropped either way
+    c_ref, c_skip = {}, {}
+    Wr, kr = orc.recursive_orth_svd(W, "diag", d, counters=c_ref)
+    Ws, ks = orc.recursive_orth_svd(W, "diag", d, counters=c_skip, skip_final=True)
+    assert ks == kr == m - 1
+    assert np.max(np.abs(Ws.T @ (d[:, None] * Ws) - np.eye(ks))) < 2e-13
+    # same span: the B-projector onto each output reproduces the other
+    assert np.max(np.abs(Wr @ (Wr.T @ (d[:, None] * Ws)) - Ws)) < 1e-12
+    assert c_skip["update"] < c_ref["update"]
+    assert c_skip["gram"] == c_ref["gram"]
+    Q = _b_orthonormal(n, 12, d)
+    Wd = RNG.standard_normal((n, 8))
+    Dr, pr = orc.deflate(Wd, Q, "diag", d)
+    Ds, ps = orc.deflate(Wd, Q, "diag", d, skip_final=True)
+    assert ps <= pr and Ds.shape == Dr.shape
+    assert np.max(np.abs(Q.T @ (d[:, None] * Ds))) <= 1e-13
+    assert np.max(np.abs(Ds - Dr)) < 1e-12
+
+
 def test_recursive_orth_drops_dependent_columns():
     n = 100
     W = RNG.standard_normal((n, 20))
