@@ -20,6 +20,17 @@ hipError_t scatter_values(int64_t nnz, const int32_t *map, const double *src, do
     } while (0)
 
 // ------------------------------------------------------------------ Stager
+// Waits for the stream by polling it: the host decisions of STEP 2 (leaf
+// eigensolves, pass tests) wait on a small download about twenty times per
+// iteration, and a blocking wait wakes up tens of microseconds after the copy
+// has finished.
+static hipError_t spin_wait(hipStream_t st) {
+    for (;;) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
 hipError_t Stager::upload(void *dst, const void *src, size_t bytes) {
     if (bytes == 0) return hipSuccess;
     const size_t need = (bytes + 255) / 256 * 256;
@@ -55,14 +66,14 @@ hipError_t Stager::download(void *dst, const void *src, size_t bytes) {
         }
     }
     GCGE_TRY(hipMemcpyAsync(ring + off, src, bytes, hipMemcpyDeviceToHost, st));
-    GCGE_TRY(hipStreamSynchronize(st));
+    GCGE_TRY(spin_wait(st));
     std::memcpy(dst, ring + off, bytes);
     off = 0;
     return hipSuccess;
 }
 
 hipError_t Stager::sync() {
-    GCGE_TRY(hipStreamSynchronize(st));
+    GCGE_TRY(spin_wait(st));
     off = 0;
     return hipSuccess;
 }
