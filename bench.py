@@ -208,6 +208,35 @@ def pmc_means(d, counter):
     return out
 
 
+def summarize_gaps(d, min_gap_us=20.0, top=8):
+    """Markdown summary of the idle time between kernels in a rocprofv3
+    --kernel-trace run (directory d): busy fraction of the traced span and the
+    gaps longer than min_gap_us, grouped by the kernel pair around them."""
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True))[-1]
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                for r in csv.DictReader(open(f)))
+    t0, t1 = iv[0][0], max(b for _, b, _ in iv)
+    end, busy, prev = iv[0][1], iv[0][1] - iv[0][0], iv[0][2]
+    gap_ns, gap_n = {}, {}
+    for a, b, nm in iv[1:]:
+        if a - end > min_gap_us * 1e3:
+            key = f"`{prev}` → `{nm}`"
+            gap_ns[key] = gap_ns.get(key, 0) + (a - end)
+            gap_n[key] = gap_n.get(key, 0) + 1
+        busy += max(0, b - max(a, end))
+        end = max(end, b)
+        prev = nm
+    lines = [f"traced span {(t1 - t0) / 1e6:.1f} ms, kernels busy {busy / 1e6:.1f} ms "
+             f"({100.0 * busy / (t1 - t0):.1f} %), {len(iv)} dispatches; "
+             f"gaps over {min_gap_us:g} us: {sum(gap_ns.values()) / 1e6:.1f} ms in {sum(gap_n.values())}", "",
+             "| before → after | gaps | total ms | average us |", "|---|---:|---:|---:|"]
+    for k in sorted(gap_ns, key=lambda k: -gap_ns[k])[:top]:
+        lines.append(f"| {k} | {gap_n[k]} | {gap_ns[k] / 1e6:.1f} | {gap_ns[k] / gap_n[k] / 1e3:.1f} |")
+    return "\n".join(lines)
+
+
 def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
     """HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch),
     each scaled by what the counter reads for a plain streaming kernel that reads and
@@ -261,6 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown table of a rocprofv3 --stats run")
+    ap.add_argument("--summarize-gaps", metavar="DIR",
+                    help="print the busy fraction and the idle gaps between kernels of a rocprofv3 --kernel-trace run")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
                                                             "COPY_WRITE_DIR"),
                     help="write the per-kernel HBM traffic of rocprofv3 --pmc runs to profiles/kernel_traffic.json")
@@ -269,6 +300,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_gaps:
+        print(summarize_gaps(args.summarize_gaps))
         return
     if args.summarize_traffic:
         t = summarize_traffic(*args.summarize_traffic, args.copy_bytes)
