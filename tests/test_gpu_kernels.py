@@ -166,6 +166,22 @@ def test_gemm_in_place_row_transform(g, s0, k, kout):
     assert np.array_equal(out[:, :s0], W[:, :s0]) and np.array_equal(out[:, s0 + kout:], W[:, s0 + kout:])
 
 
+@pytest.mark.parametrize("k,kout", [(16, 16), (13, 9), (6, 8), (25, 30)])
+def test_gemm_in_place_with_beta(g, k, kout):
+    """Y = alpha X S + beta Y with Y the same columns as X (each row is read
+    before it is written), for the 8-, 16- and 32-lane row kernels."""
+    n = 4099
+    W = RNG.standard_normal((n, 40))
+    S = RNG.standard_normal((k, kout))
+    Wd = dev(W)
+    g.gemm_update(Wd[:, 2:2 + k], S, Wd[:, 2:2 + kout], alpha=0.75, beta=-0.5)
+    out = host(Wd)
+    ref = 0.75 * (W[:, 2:2 + k] @ S) - 0.5 * W[:, 2:2 + kout]
+    bound = 0.75 * (np.abs(W[:, 2:2 + k]) @ np.abs(S)) + 0.5 * np.abs(W[:, 2:2 + kout])
+    assert np.all(np.abs(out[:, 2:2 + kout] - ref) <= 1e-13 * bound)
+    assert np.array_equal(out[:, :2], W[:, :2]) and np.array_equal(out[:, 2 + kout:], W[:, 2 + kout:])
+
+
 @pytest.mark.parametrize("maxit", [1, 2, 5, 30])
 def test_cg_fp64_matches_oracle(g, maxit):
     A = wl.laplace3d_7pt(10)
