@@ -18,8 +18,8 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "csrc", "jacobi.c")
-_SO = os.path.join(_HERE, "_build", "liboracle_jacobi.so")
+_SRCS = [os.path.join(_HERE, "csrc", f) for f in ("jacobi.c", "sparse.c")]
+_SO = os.path.join(_HERE, "_build", "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -41,9 +41,15 @@ PINS = {
                           "m/4 - 1 Gram count for c = 16 (Section 3.1 count)",
     "modified_block_orth": "W^T B W = I, X0^T B W = 0, span preservation, m + m/b - 1 count (Section 3.1)",
     "assemble_abar": "equals the explicit V_u^T A V_u on a random pencil after one exact GCG step",
-    "p_hat": "[xhat, phat]^T [xhat, phat] = I; zero rows; rank loss on a complete xhat",
+    "p_hat": "hand-derived coefficients of two small cases (the zeroed rows and the column window of eq. "
+             "CP_tilde both matter); [xhat, phat]^T [xhat, phat] = I; rank loss on a complete xhat",
     "eig_grad": "central finite differences of pencil_eigs on small random pencils",
-    "moving_memory": "parity unpinned beyond direct evaluation of the paper's formula (weak pin)",
+    "lanczos.lanczos_eigs": "closed-form 2D/3D Laplacian and Q1 spectra with their multiplicities (a "
+                            "block of 8 holds the sixfold clusters); the dense Jacobi oracle on diagonal-B and "
+                            "variable-coefficient pencils (eigenvalues and eigenvectors); B-orthonormality and "
+                            "explicit residuals",
+    "lanczos.csr_spmm": "dense matrix product",
+    "lanczos.csr_cg": "numpy.linalg.solve on SPD systems; zero right-hand side; breakdown on an indefinite matrix",
     "amg.aggregate": "hand-derived aggregates of the 1D Laplacian and of small graphs (strongest-link "
                      "rule, tie margin, weak links); partition of the rows",
     "amg.amg_setup": "hand-derived smoothed prolongator column (1D); P_t^T P_t = I; the V-cycle checks below",
@@ -63,12 +69,17 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        need = (not os.path.exists(_SO)) or os.path.getmtime(_SO) < os.path.getmtime(_SRC)
+        need = (not os.path.exists(_SO)) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS)
         if need:
             build()
         lib = ctypes.CDLL(_SO)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
         lib.oracle_jacobi_eigh.restype = ctypes.c_int
-        lib.oracle_jacobi_eigh.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_jacobi_eigh.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int]
+        lib.oracle_spmm.restype = None
+        lib.oracle_spmm.argtypes = [i64, vp, vp, vp, ctypes.c_int, vp, vp]
+        lib.oracle_cg.restype = ctypes.c_int
+        lib.oracle_cg.argtypes = [i64, vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int, vp]
         _lib = lib
         return lib
 
@@ -77,7 +88,7 @@ def build():
     """Compile the oracle's C part (gcc, OpenMP) into oracle/_build."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
     tmp = _SO + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
     os.replace(tmp, _SO)
 
 
@@ -432,14 +443,16 @@ def recursive_orth_svd(X, bkind, B, c=None, leaf_tol=1e-13, int_tol=1e-13, max_p
     return X[:, :kept].copy(), kept
 
 
-def modified_block_orth(X, X0, bkind, B, b=None, tol=1e-13, max_pass=3, drop_tol=1e-10, counters=None):
+def modified_block_orth(X, X0, bkind, B, b=None, tol=1e-13, max_pass=3, drop_tol=1e-4, counters=None):
     """Modified block orthogonalization (Algorithm 2): deflate the B-orthonormal
     X0 from X (repeated), then for blocks X_1..X_l of b columns: orthogonalize
     X_k by modified Gram-Schmidt, then deflate X_k from the later blocks
     (repeated).  b defaults to min(m/4, 200).  A column whose B-norm after
     orthogonalization is at most drop_tol times its B-norm on entry (after the
     X0 deflation) is linearly dependent and is dropped (later columns move
-    forward).  Returns (X_out, kept)."""
+    forward).  The default drop_tol = 1e-4 is the threshold of the
+    recursive orthogonalization in squared form (a squared B-norm of 1e-8 of
+    the unit input; see recursive_orth_svd).  Returns (X_out, kept)."""
     X = np.array(X, dtype=np.float64)
     m = X.shape[1]
     if counters is None:
@@ -607,16 +620,10 @@ def eig_grad_diag(X, lam, g):
     return np.sum(X * X * w[None, :], axis=1)
 
 
-def moving_memory(sizeX, block_size, max_proj_dim):
-    """Number of doubles per process the small dense problem needs with the
-    moving mechanism (eq. equ:moving_mem, Section 3.3)."""
-    return ((sizeX + 2 * block_size) + 2 * max_proj_dim ** 2 + 10 * max_proj_dim
-            + sizeX * block_size)
-
 
 __all__ = [
     "build", "jacobi_eigh", "cholesky", "solve_lower", "solve_lower_t", "spmm", "spmm_rows", "apply_b",
     "dense_b", "shifted_spmm", "gram", "b_gram", "residual", "relative_residuals", "converged_prefix",
     "cg_columnwise", "deflate", "recursive_orth_svd", "modified_block_orth", "assemble_abar",
-    "rayleigh_ritz", "p_hat", "pencil_eigs", "eig_grad", "eig_grad_diag", "moving_memory",
+    "rayleigh_ritz", "p_hat", "pencil_eigs", "eig_grad", "eig_grad_diag",
 ]

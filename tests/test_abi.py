@@ -108,3 +108,16 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_host_p_hat_hand_derived(lib):
+    """The library's STEP 5 coefficients on the hand-derived case of eq.
+    CP_tilde (see tests/test_oracle_pins.py): phat = (-2,0,1,1,0)/sqrt6."""
+    import paper_2111_06552_amd as g
+    a = np.array([1.0, 0.0, 1.0, 1.0, 0.0]) / np.sqrt(3.0)
+    b = np.array([0.0, 1.0, 0.0, 0.0, 1.0]) / np.sqrt(2.0)
+    ph = g.p_hat(np.stack([a, b], axis=1), 0, 1, 1)
+    ref = np.array([-2.0, 0.0, 1.0, 1.0, 0.0]) / np.sqrt(6.0)
+    assert ph.shape == (5, 1)
+    assert np.max(np.abs(np.sign(ph[:, 0] @ ref) * ph[:, 0] - ref)) < 1e-14
+    assert g.p_hat(np.stack([a, b], axis=1), 1, 1, 1).shape[1] == 0

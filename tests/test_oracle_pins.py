@@ -389,6 +389,42 @@ def test_p_hat_orthonormal_and_complete_basis_gives_empty():
     assert orc.p_hat(Q, 0, 5, 5).shape[1] == 0
 
 
+def _same_columns_up_to_sign(P, Ref):
+    assert P.shape == Ref.shape
+    for j in range(Ref.shape[1]):
+        s = 1.0 if P[:, j] @ Ref[:, j] >= 0 else -1.0
+        assert np.max(np.abs(s * P[:, j] - Ref[:, j])) < 1e-14, (j, P[:, j], Ref[:, j])
+
+
+def test_p_hat_hand_derived_single_column():
+    """Eq. CP_tilde by hand: xhat = [a, b] with a = (1,0,1,1,0)/sqrt3 and
+    b = (0,1,0,0,1)/sqrt2, next active column 0 (shift 0), current active block
+    one row (row 0 zeroed): ptilde = (0,0,1,1,0)/sqrt3; removing a (a.ptilde =
+    2/3) leaves (-2,0,1,1,0)/(3 sqrt3), b-free, i.e. phat = (-2,0,1,1,0)/sqrt6.
+    Zeroing the wrong row (row 2) would give (1,0,-2,1,0)/sqrt6, and the wrong
+    column window (shift 1: ptilde = b, already in span(xhat)) no column."""
+    a = np.array([1.0, 0.0, 1.0, 1.0, 0.0]) / np.sqrt(3.0)
+    b = np.array([0.0, 1.0, 0.0, 0.0, 1.0]) / np.sqrt(2.0)
+    xhat = np.stack([a, b], axis=1)
+    ph = orc.p_hat(xhat, 0, 1, 1)
+    _same_columns_up_to_sign(ph, np.array([[-2.0, 0.0, 1.0, 1.0, 0.0]]).T / np.sqrt(6.0))
+    assert orc.p_hat(xhat, 1, 1, 1).shape[1] == 0
+
+
+def test_p_hat_hand_derived_two_columns():
+    """Two active columns and two zeroed rows: xhat = [a, b, c] with a, b as
+    above padded by a zero and c = e_6.  ptilde_1 = a with rows 0-1 zeroed
+    -> (-2,0,1,1,0,0)/sqrt6 as above; ptilde_2 = b with rows 0-1 zeroed =
+    e_5/sqrt2, minus b/2 -> (0,-1,0,0,1,0)/sqrt2 (orthogonal to the first)."""
+    a = np.array([1.0, 0.0, 1.0, 1.0, 0.0, 0.0]) / np.sqrt(3.0)
+    b = np.array([0.0, 1.0, 0.0, 0.0, 1.0, 0.0]) / np.sqrt(2.0)
+    c = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 1.0])
+    ph = orc.p_hat(np.stack([a, b, c], axis=1), 0, 2, 2)
+    ref = np.stack([np.array([-2.0, 0.0, 1.0, 1.0, 0.0, 0.0]) / np.sqrt(6.0),
+                    np.array([0.0, -1.0, 0.0, 0.0, 1.0, 0.0]) / np.sqrt(2.0)], axis=1)
+    _same_columns_up_to_sign(ph, ref)
+
+
 def test_structured_abar_equals_explicit_projection():
     # One exact GCG step on a small pencil: V_old = [X, P, W] B-orthonormal,
     # RR -> (lam, xhat), X_new = V_old xhat, P_new = V_old phat, W_new a fresh
@@ -474,16 +510,6 @@ def test_eig_grad_b_csr_and_diag():
     lp, _ = orc.pencil_eigs(A2, "diag", dp, 3)
     lm, _ = orc.pencil_eigs(A2, "diag", dm, 3)
     assert abs((g2 @ lp - g2 @ lm) / (2 * step) - gd[j]) < 1e-6 * max(1.0, abs(gd[j]))
-
-
-def test_moving_memory_formula_weak_pin():
-    # eq. equ:moving_mem with sizeX = 3 bs, maxProjDim = 5 bs (moving) is far below
-    # the no-moving value with sizeX = nev + 3 bs, maxProjDim = sizeX + 2 bs.
-    bs, nev = 200, 5000
-    moving = orc.moving_memory(3 * bs, bs, 5 * bs)
-    full = orc.moving_memory(nev + 3 * bs, bs, nev + 5 * bs)
-    assert moving == (3 * bs + 2 * bs) + 2 * (5 * bs) ** 2 + 10 * 5 * bs + 3 * bs * bs
-    assert moving < full / 10
 
 
 def test_modified_block_orth_drops_columns_dependent_on_earlier_blocks():
