@@ -34,6 +34,7 @@
 #ifndef GCGE_H
 #define GCGE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -230,6 +231,27 @@ int gcge_residual(const gcge_csr *A, int b_kind, const void *B, const double *la
  * reproducible). */
 int gcge_gram(int64_t n, const double *X, int64_t ldx, int m, const double *Y, int64_t ldy, int k,
               const double *d, double *C, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the block
+ * inner product of gcge_gram with no allocation and no host synchronization.
+ * C is DEVICE memory here, double[m*k] row-major (C[i*k + j] = x_i^T D y_j),
+ * written asynchronously on stream; the other arguments are those of
+ * gcge_gram.  The kernels are gcge_gram's; their per-chunk partial tiles live
+ * in a library-owned device array of GCGE_NOALLOC_SCRATCH_BYTES (each device
+ * the library runs on holds its own until the process ends), not in the
+ * workspace gcge_gram grows.  When that array holds fewer chunks than
+ * gcge_gram would use, each work-group sums a longer chunk of rows, so the
+ * result can differ from gcge_gram's in the last bits (it is still fixed for
+ * fixed sizes).  Every call on one device uses that device's array: calls
+ * that overlap in time on one device (several streams or threads) race and
+ * must be serialized by the caller.  Nothing in the array has to start at
+ * zero.  INVALID_ARG when m > 3072, or when one chunk of the m x k partial
+ * tiles (ceil(m/64) * ceil(k/64) tiles of 32 KiB for m or k above 32) does
+ * not fit the array; HIP on a launch failure. */
+#define GCGE_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int gcge_gram_noalloc(int64_t n, const double *X, int64_t ldx, int m, const double *Y, int64_t ldy, int k,
+                      const double *d, double *C, void *stream);
 
 /* Y = alpha X S + beta Y with S host double[m*k] row-major (S[i*k + j]):
  * the dense multi-vector linear combination of the Ritz rotation

@@ -310,6 +310,27 @@ def gram(X: torch.Tensor, Y: torch.Tensor, d: torch.Tensor | None = None) -> np.
     return C
 
 
+def gram_noalloc(X: torch.Tensor, Y: torch.Tensor, d: torch.Tensor | None = None,
+                 C: torch.Tensor | None = None) -> torch.Tensor:
+    """X^T diag(d) Y into the device tensor C (m x k float64, contiguous), through the
+    entry point that allocates nothing (partials in the library's fixed device array)."""
+    _check_dev(X, torch.float64, "X")
+    _check_dev(Y, torch.float64, "Y")
+    if d is not None:
+        _check_dev(d, torch.float64, "d")
+    m, k = X.shape[1], Y.shape[1]
+    if C is None:
+        C = torch.empty((m, k), dtype=torch.float64, device=X.device)
+    _check_dev(C, torch.float64, "C")
+    if tuple(C.shape) != (m, k) or not C.is_contiguous():
+        raise ValueError("C must be a contiguous m x k tensor")
+    px, ldx = _rowmajor(X, "X")
+    py, ldy = _rowmajor(Y, "Y")
+    _lib.check(_L().gcge_gram_noalloc(X.shape[0], px, ldx, m, py, ldy, k, _p(d), _p(C),
+                                      ctypes.c_void_p(_stream(X.device))))
+    return C
+
+
 def gemm_update(X: torch.Tensor, S, Y: torch.Tensor | None = None, alpha: float = 1.0, beta: float = 0.0):
     """Y = alpha X S + beta Y with S a host (m x k) array."""
     _check_dev(X, torch.float64, "X")

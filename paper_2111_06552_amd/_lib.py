@@ -28,7 +28,11 @@ EXPORTED = [
     "gcge_spmm_f32", "gcge_shifted_spmm", "gcge_residual", "gcge_gram", "gcge_gemm_update", "gcge_cg",
     "gcge_orth", "gcge_orth_mbo", "gcge_small_eigh", "gcge_dense_eig", "gcge_p_hat", "gcge_pattern_grad",
     "gcge_amg_create", "gcge_amg_levels", "gcge_amg_aggregates", "gcge_amg_apply", "gcge_pcg", "gcge_amg_destroy",
+    "gcge_gram_noalloc",
 ]
+
+# Size of the library's device array behind gcge_gram_noalloc (GCGE_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class GcgeError(RuntimeError):
@@ -101,6 +105,8 @@ def load():
                                       c_int64, c_void_p, c_void_p, c_void_p]),
             "gcge_gram": (c_int, [c_int64, c_void_p, c_int64, c_int, c_void_p, c_int64, c_int, c_void_p, c_void_p,
                                   c_void_p]),
+            "gcge_gram_noalloc": (c_int, [c_int64, c_void_p, c_int64, c_int, c_void_p, c_int64, c_int, c_void_p,
+                                          c_void_p, c_void_p]),
             "gcge_gemm_update": (c_int, [c_int64, c_void_p, c_int64, c_int, c_void_p, c_int, c_double, c_double,
                                          c_void_p, c_int64, c_void_p]),
             "gcge_cg": (c_int, [P(Csr), c_int, c_void_p, c_double, c_void_p, c_int64, c_int, c_int, c_double, c_int,

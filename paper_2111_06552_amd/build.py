@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgcge.so")
 
-SOURCES = ["kernels.hip", "eig.hip", "operator.cpp", "solver.cpp", "dense.cpp", "amg.cpp"]
+SOURCES = ["kernels.hip", "eig.hip", "noalloc.hip", "operator.cpp", "solver.cpp", "dense.cpp", "amg.cpp"]
 ARCH = os.environ.get("GCGE_OFFLOAD_ARCH", "gfx950")
 
 

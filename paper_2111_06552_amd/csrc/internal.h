@@ -71,6 +71,9 @@ struct Workspace {
     void release();
 };
 
+// Text returned by gcge_last_error(NULL) on the calling thread.
+void set_thread_error(const std::string &msg);
+
 // ------------------------------------------------------------------ launches
 // All launches are asynchronous on `st`.
 
@@ -159,6 +162,14 @@ hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *p
 // C (m x k, row-major, ldc) = X^T diag(d) Y with X given as segments.
 hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
                 int64_t ldc, Workspace &ws, hipStream_t st);
+// The same product with the per-chunk partial tiles in the caller's device
+// buffer part (part_bytes): when it holds fewer chunks than gram() would use,
+// each work-group takes a longer chunk of rows (the summation order then
+// differs from gram()'s).  With need != nullptr, *need receives the bytes of
+// partials used, and a null part only plans (nothing is launched).
+// hipErrorInvalidValue when not even one chunk fits or X has too many tiles.
+hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
+                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st);
 
 // Y = alpha * X S + beta * Y; X segments (m = total columns), S device row-major
 // (m x lds), Y n x k.

@@ -1410,8 +1410,9 @@ __global__ __launch_bounds__(512) void k_gram_lds(GramParams P) {
             }
 }
 
-hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
-                int64_t ldc, Workspace &ws, hipStream_t st) {
+hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
+                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st) {
+    if (need) *need = 0;
     const int m = X.total();
     if (m == 0 || k == 0) return hipSuccess;
     int MB, NB;
@@ -1437,18 +1438,26 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     P.nyt = (k + TN - 1) / TN;
     P.d = d;
     const int tiles = P.ntile * P.nyt;
+    const size_t tile_bytes = (size_t)TM * TN * sizeof(double);
     // one residency wave of work-groups for the large-tile kernel
     const int cap = lds ? resident_grid((const void *)k_gram_lds<false>, 1 << 30, 512) : 2048;
     int nchunk = std::max(1, cap / tiles);
     nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, (n + 255) / 256));
+    // a caller-sized partial buffer may hold fewer chunks (longer chunks, same kernels)
+    const size_t fit = part_bytes / ((size_t)tiles * tile_bytes);
+    if (fit < 1) return hipErrorInvalidValue;
+    if ((size_t)nchunk > fit) nchunk = (int)fit;
     int64_t rp = (n + nchunk - 1) / nchunk;
     rp = (rp + 31) / 32 * 32;
     nchunk = (int)((n + rp - 1) / rp);
     P.nchunk = nchunk;
     P.rows_per = rp;
-    hipError_t e = ws.ensure_part((size_t)tiles * nchunk * TM * TN * sizeof(double));
-    if (e != hipSuccess) return e;
-    P.part = ws.part;
+    if (need) {
+        *need = (size_t)tiles * nchunk * tile_bytes;
+        if (part == nullptr) return hipSuccess;
+    }
+    if (part == nullptr) return hipErrorInvalidValue;
+    P.part = part;
     dim3 grid(tiles * nchunk), block(256);
     if (lds) {
         if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, dim3(512), 0, st, P);
@@ -1465,6 +1474,16 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
     GCGE_GRAM(2, 2)
 #undef GCGE_GRAM
     return hipGetLastError();
+}
+
+hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
+                int64_t ldc, Workspace &ws, hipStream_t st) {
+    size_t need = 0;
+    hipError_t e = gram_into(n, X, Y, ldy, k, d, C, ldc, nullptr, SIZE_MAX, &need, st);
+    if (e != hipSuccess || need == 0) return e;
+    e = ws.ensure_part(need);
+    if (e != hipSuccess) return e;
+    return gram_into(n, X, Y, ldy, k, d, C, ldc, ws.part, ws.part_bytes, nullptr, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -836,6 +836,10 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         return GCGE_ERR_INTERNAL;                                            \
     }
 
+namespace gcge {
+void set_thread_error(const std::string &msg) { g_thread_err = msg; }
+}  // namespace gcge
+
 static bool csr_ok(const gcge_csr *A) {
     return A && A->n >= 1 && A->nnz >= 0 && A->rowptr && (A->nnz == 0 || (A->colind && A->val)) &&
            A->nnz <= INT32_MAX;
