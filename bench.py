@@ -12,8 +12,12 @@ Prints one JSON line.  Fields beyond the required ones:
   mixed         the FP32-inner-CG solve: time, speedup and eigenvalue agreement
   solve         iteration counts, residual and B-orthonormality of the FP64 solve
   roofline      the dominant kernel's achieved rate from HIP-event timings of
-                every launch in the timed solves
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+                every launch of one instrumented solve run after the timed
+                ones (the timed solves carry no instrumentation); HBM rates are
+                also given as a fraction of a copy measured on the same GPU
+  cpu_baseline  the CPU oracle (block Lanczos) solving the same generator on a
+                reduced grid on the host cores, with the GPU solve of that very
+                input timed beside it
 """
 from __future__ import annotations
 
@@ -124,7 +128,7 @@ def sum_prof(stats):
     return out
 
 
-def cpu_baseline(A, spmm_columns, budget_s):
+def spmm_extrapolation(A, spmm_columns, budget_s):
     """Oracle SpMM on the full operator, timed on a sample of columns and
     scaled to the number of columns the GPU solve pushed through sparse
     products (the solve's dominant work; Gram, orthogonalization and the dense
@@ -144,10 +148,82 @@ def cpu_baseline(A, spmm_columns, budget_s):
         if el > budget_s or reps >= 20:
             break
     per_col = el / (reps * k)
-    return {"value": per_col * spmm_columns, "unit": "s", "cores": 1, "kind": "oracle",
+    return {"value": per_col * spmm_columns, "unit": "s", "cores": 1,
             "sample": f"oracle.spmm (numpy, one thread) of the full operator on {k} columns x {reps} repetitions "
                       f"({el:.1f} s), scaled to the {spmm_columns} SpMM columns of the FP64 GPU solve; "
                       f"excludes the orthogonalization and Rayleigh-Ritz work"}
+
+
+def host_threads():
+    """Threads the oracle's OpenMP code runs with."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    try:
+        return int(v) if v else (os.cpu_count() or 1)
+    except ValueError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(g, workload, grid, dev):
+    """The oracle solving the benchmark's generator on a reduced grid (the
+    block Lanczos reference eigensolver on the host cores, all nev pairs to an
+    explicit relative residual of 1e-12 or its rounding floor), and the GPU
+    solver on that same input in the benchmark's configuration."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from oracle.lanczos import lanczos_eigs
+    A, bkind, B, p = wl.build_workload(workload, grid)
+    nev, bs, tol = p["nev"], p["block_size"], p["tol"]
+    t0 = time.perf_counter()
+    lam_o, _, info = lanczos_eigs(A, bkind, B, nev)
+    cpu_s = time.perf_counter() - t0
+    Ad = g.DeviceCsr.from_csr(A, dev)
+    Bd = None
+    if bkind == "diag":
+        Bd = torch.as_tensor(B, dtype=torch.float64, device=dev)
+    elif bkind == "csr":
+        Bd = g.DeviceCsr.from_csr(B, dev)
+    with g.Solver(Ad, Bd, nev, tol, block_size=bs, moving=int(p["moving"])) as s:
+        s.solve()                      # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lam, _, st = s.solve()
+        torch.cuda.synchronize()
+        gpu_s = time.perf_counter() - t
+    err = float(np.max(np.abs(lam.numpy() - lam_o) / np.abs(lam_o)))
+    return {"value": cpu_s, "unit": "s", "cores": host_threads(), "kind": "oracle",
+            "sample": f"oracle.lanczos.lanczos_eigs (block Lanczos, OpenMP CSR products and CG) solving the "
+                      f"{workload} generator on a {grid}^3 grid (n = {A.n}), all {nev} pairs; "
+                      f"{info['steps']} Lanczos steps, {info['cg_iterations']} CG iterations",
+            "gpu_same_input_s": gpu_s, "gpu_speedup": cpu_s / gpu_s, "gpu_iterations": st["iterations"],
+            "max_eig_rel_diff_gpu_vs_oracle": err}
+
+
+def copy_peak_gbs(dev, nbytes=1 << 30, reps=10):
+    """HBM rate of a plain device copy (bytes read + bytes written per second)."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def add_measured_peak(entry, copy_gbs):
+    if entry is not None and entry.get("bound") == "hbm" and copy_gbs:
+        entry["peak_measured_copy"] = copy_gbs
+        entry["frac_of_measured_copy"] = entry["achieved"] / copy_gbs
+    return entry
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2111_06552_amd", "csrc", "kernels.hip")
@@ -288,7 +364,10 @@ def main():
                     help="1: Algorithm 3's pass loops stop before the update of a pass that already "
                          "meets the tolerance (the paper's listing applies it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--cpu-grid", type=int, default=32,
+                    help="grid of the reduced input that the CPU oracle and the GPU both solve for cpu_baseline")
+    ap.add_argument("--cpu-budget-s", type=float, default=5.0,
+                    help="time spent on the SpMM sample of the extrapolated CPU figure")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a markdown table of a rocprofv3 --stats run")
     ap.add_argument("--summarize-gaps", metavar="DIR",
                     help="print the busy fraction and the idle gaps between kernels of a rocprofv3 --kernel-trace run")
@@ -336,7 +415,9 @@ def main():
     evecs = torch.empty((A.n, nev), dtype=torch.float64, device=dev)
 
     def run(prec, steps, warmup):
-        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=1, orth=args.orth,
+        """Timed solves without instrumentation, then one solve with every
+        launch of the main kernel classes bracketed by HIP events."""
+        opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=0, orth=args.orth,
                     cg_max_iter=args.cg_max_iter, cg_rel_tol=args.cg_rel_tol, shift=args.shift,
                     precond=args.precond, orth_skip_final=args.orth_skip_final)
         with g.Solver(Ad, Bd, nev, tol, **opts) as s:
@@ -354,9 +435,18 @@ def main():
                 stats.append(st)
                 log(f"[bench] {prec} step {i}: {times[-1]*1e3:.0f} ms, {st['iterations']} iterations, "
                     f"{st['cg_iterations']} CG iterations, max rel residual {st['max_rel_residual']:.2e}")
-            return np.array(times), stats, lam.numpy().copy()
+            s.set_options(profile=1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, _, sp = s.solve(evecs)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t
+            log(f"[bench] {prec} instrumented solve: {tp*1e3:.0f} ms")
+            return np.array(times), stats, lam.numpy().copy(), sp, tp
 
-    t64, s64, lam64 = run("fp64", args.steps, args.warmup)
+    copy_gbs = copy_peak_gbs(dev)
+    log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
+    t64, s64, lam64, sp64, tp64 = run("fp64", args.steps, args.warmup)
     out = {
         "metric": METRIC, "value": float(t64.mean()), "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": float(t64.mean() * 1e3), "higher_is_better": False,
@@ -373,28 +463,36 @@ def main():
                                        "max_rel_residual", "orth_error")}
     out["solve"]["step_ms"] = {k: round(v, 2) for k, v in st["time_ms"].items()}
     out["solve"]["times_s"] = [round(x, 4) for x in t64.tolist()]
-    # roofline from every launch of the timed solves
-    prof = sum_prof(s64)
+    out["solve"]["instrumented_solve_s"] = round(tp64, 4)
+    # rooflines from every launch of the instrumented solve
+    prof = sum_prof([sp64])
     roof, name = dominant_roofline(prof, A.n, A.nnz, bs=bs)
     if roof is not None and roof.get("bound") == "hbm":
         roof["traffic"] = measured_traffic(roof["kernel"])
-    out["roofline"] = roof
-    out["kernel_rooflines"] = {c: class_roofline(c, prof[c], A.n, A.nnz, bs=bs) for c in prof}
-    out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"] / args.steps, 2) for c in prof}
-    out["cg_iteration_roofline"] = cg_iteration_roofline(out["kernel_rooflines"])
+    out["roofline"] = add_measured_peak(roof, copy_gbs)
+    out["kernel_rooflines"] = {c: add_measured_peak(class_roofline(c, prof[c], A.n, A.nnz, bs=bs), copy_gbs)
+                               for c in prof}
+    out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"], 2) for c in prof}
+    out["cg_iteration_roofline"] = add_measured_peak(cg_iteration_roofline(out["kernel_rooflines"]), copy_gbs)
+    out["copy_peak_gbs"] = copy_gbs
     if not args.no_mixed:
-        tm, sm, lamm = run("mixed", args.steps, args.warmup)
+        tm, sm, lamm, spm, tpm = run("mixed", args.steps, args.warmup)
         out["mixed"] = {"value": float(tm.mean()), "unit": "s", "ms_per_step": float(tm.mean() * 1e3),
                         "speedup_vs_fp64": float(t64.mean() / tm.mean()),
                         "max_eig_rel_diff_vs_fp64": float(np.max(np.abs(lamm - lam64) / np.abs(lam64))),
                         "iterations": sm[-1]["iterations"], "cg_iterations": sm[-1]["cg_iterations"],
                         "max_rel_residual": sm[-1]["max_rel_residual"], "dtype": "f32 inner CG, f64 elsewhere"}
-        profm = sum_prof(sm)
-        out["mixed"]["kernel_rooflines"] = {c: class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs)
+        profm = sum_prof([spm])
+        out["mixed"]["kernel_rooflines"] = {c: add_measured_peak(class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs),
+                                                                 copy_gbs)
                                             for c in ("cg_spmm", "cg_update_r", "cg_update_xp")}
-        out["mixed"]["cg_iteration_roofline"] = cg_iteration_roofline(out["mixed"]["kernel_rooflines"])
+        out["mixed"]["cg_iteration_roofline"] = add_measured_peak(
+            cg_iteration_roofline(out["mixed"]["kernel_rooflines"]), copy_gbs)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, int(st["spmm_columns"]), args.cpu_budget_s)
+        log(f"[bench] cpu baseline: oracle on the {args.cpu_grid}^3 grid, {host_threads()} threads")
+        out["cpu_baseline"] = cpu_baseline(g, args.workload, args.cpu_grid, dev)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.1f} s (GPU {out['cpu_baseline']['gpu_same_input_s']:.3f} s)")
+        out["cpu_spmm_extrapolation"] = spmm_extrapolation(A, int(st["spmm_columns"]), args.cpu_budget_s)
     print(json.dumps(out), flush=True)
 
 

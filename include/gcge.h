@@ -111,7 +111,10 @@ typedef struct {
  * The library copies the values it needs (union pattern of A and B, shifted
  * operator, FP32 copies) at creation; the borrowed arrays are read again only
  * by gcge_eig_grad (patterns).  Errors: INVALID_ARG (n < 1, nev < 1,
- * nev > n, tol <= 0, nnz < 0, a pointer NULL), OOM, HIP. */
+ * nev > n, tol <= 0, nnz < 0, a pointer NULL), NOT_SPD (a diagonal entry of
+ * B that is not positive, not finite, or, for CSR B, not stored: B cannot be
+ * positive definite; a B with a positive diagonal is not tested further), OOM,
+ * HIP. */
 int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double tol, gcge_handle *out);
 
 /* Integer options (defaults in brackets; paper defaults cited):
@@ -175,7 +178,9 @@ int gcge_set_initial_vectors(gcge_handle h, const double *X0, int64_t ld, int k)
 int gcge_solve(gcge_handle h, double *evals, double *evecs, int64_t ld, gcge_stats *stats);
 
 /* Replace the values of A (and of B: a device double[nnzB] for CSR, or the
- * device diagonal for DIAG; NULL keeps B) keeping the sparsity patterns. */
+ * device diagonal for DIAG; NULL keeps B) keeping the sparsity patterns.
+ * NOT_SPD as gcge_create for the new B (the handle then holds the new values
+ * and gcge_solve must not be called before valid ones are set). */
 int gcge_update_values(gcge_handle h, const double *a_val, const void *b_val);
 
 /* Eigenvalue gradients of L = sum_i g[i] lambda_i for the pairs of the last
@@ -184,7 +189,9 @@ int gcge_update_values(gcge_handle h, const double *a_val, const void *b_val);
  * for B-normalized x_i (well separated eigenvalues).  g: host double[nev].
  * gA: device double[nnzA].  gB: device double[nnzB] (CSR B) or double[n]
  * (diagonal B) or NULL.  Each stored entry is an independent variable; for a
- * symmetric perturbation of a_jk and a_kj add both entries. */
+ * symmetric perturbation of a_jk and a_kj add both entries.  Returns
+ * GCGE_NOT_CONVERGED (gradients still written) when the last solve ended at
+ * max_iter: the formula holds for exact eigenpairs only. */
 int gcge_eig_grad(gcge_handle h, const double *g, double *gA, double *gB);
 
 void gcge_destroy(gcge_handle h);

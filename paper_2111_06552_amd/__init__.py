@@ -120,6 +120,9 @@ class Solver:
         self.last_stats = None
         self.last_evecs = None
         self._x0 = None
+        # raised by every solve() and update_values(): a gradient belongs to the
+        # solve it was taken from (GcgeEig checks it in backward)
+        self.generation = 0
 
     def set_options(self, **options):
         for k, v in options.items():
@@ -154,6 +157,7 @@ class Solver:
         evals = np.zeros(self.nev, dtype=np.float64)
         st = _lib.Stats()
         _lib.check(L.gcge_set_stream(self._h, ctypes.c_void_p(_stream(evecs.device))), self._h)
+        self.generation += 1
         rc = _lib.check(L.gcge_solve(self._h, evals.ctypes.data_as(ctypes.c_void_p), p, ld, ctypes.byref(st)),
                         self._h)
         self.last_stats = st.as_dict()
@@ -171,6 +175,7 @@ class Solver:
             _check_dev(b_val, torch.float64, "b_val")
             b_val = b_val.contiguous()
         _lib.check(_L().gcge_set_stream(self._h, ctypes.c_void_p(_stream())), self._h)
+        self.generation += 1
         _lib.check(_L().gcge_update_values(self._h, _p(a_val), _p(b_val)), self._h)
         self._keep = (a_val, b_val)
 
@@ -186,7 +191,9 @@ class Solver:
         elif self.b_kind == B_DIAG:
             gB = torch.empty(self.n, dtype=torch.float64, device=dev)
         _lib.check(_L().gcge_set_stream(self._h, ctypes.c_void_p(_stream(dev))), self._h)
-        _lib.check(_L().gcge_eig_grad(self._h, g.ctypes.data_as(ctypes.c_void_p), _p(gA), _p(gB)), self._h)
+        rc = _lib.check(_L().gcge_eig_grad(self._h, g.ctypes.data_as(ctypes.c_void_p), _p(gA), _p(gB)), self._h)
+        if rc == GCGE_NOT_CONVERGED:
+            raise GcgeError(rc, "the last solve did not converge: no gradient of unconverged pairs")
         return gA, gB
 
     def close(self):
@@ -224,11 +231,17 @@ class GcgeEig(torch.autograd.Function):
         solver.update_values(a_val.detach(), None if b_val is None else b_val.detach())
         evals, evecs, _ = solver.solve()
         ctx.solver = solver
+        ctx.generation = solver.generation
         ctx.has_b = b_val is not None
         return evals.to(a_val.device)
 
     @staticmethod
     def backward(ctx, g):
+        # the kernel reads the solver's last eigenvectors: they must be this forward's
+        if ctx.solver.generation != ctx.generation:
+            raise RuntimeError("the solver ran another solve or update_values between this forward and its "
+                               "backward; its eigenvectors no longer belong to this graph (use one solver "
+                               "per differentiated solve, or call backward first)")
         gA, gB = ctx.solver.eig_grad(g)
         return gA, (gB if ctx.has_b else None), None
 

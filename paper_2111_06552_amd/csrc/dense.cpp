@@ -1,10 +1,14 @@
 // Host dense linear algebra of the small Rayleigh-Ritz problem (Section 3.2,
 // STEP 3; the paper calls LAPACK dsyevx) and of STEP 5.  No LAPACK: the
 // symmetric eigensolver is Householder reduction to tridiagonal form followed
-// by the implicit QL iteration with Wilkinson-type shifts (the classical
-// Wilkinson-Reinsch scheme), written here from the mathematics.  Rotations of
-// one QL sweep are recorded and then applied to the eigenvector matrix in
-// parallel over its rows (OpenMP).
+// by the implicit QL iteration with Wilkinson-type shifts.  The QL iteration
+// follows the published procedure tql2 (Bowdler, Martin, Reinsch and
+// Wilkinson, "The QR and QL algorithms for symmetric matrices", Numer. Math.
+// 11, 1968; Wilkinson and Reinsch, Handbook for Automatic Computation II,
+// contribution II/3), step for step: the shift from the leading 2 x 2 block,
+// the plane rotations chasing the bulge, and the early exit when a rotation
+// radius vanishes.  Rotations of one QL sweep are recorded and then applied
+// to the eigenvector matrix in parallel over its rows (OpenMP).
 #include <omp.h>
 
 #include <algorithm>

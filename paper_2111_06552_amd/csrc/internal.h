@@ -63,7 +63,10 @@ struct Workspace {
     int *iflags = nullptr;       // CG counters
     double *pinned = nullptr;    // pinned host staging (hipHostMalloc)
     size_t pinned_bytes = 0;
+    char *orth = nullptr;        // STEP 2 device state: coefficient blocks and flags
+    size_t orth_bytes = 0;
     hipError_t ensure_part(size_t bytes);
+    hipError_t ensure_orth(size_t bytes);
     hipError_t ensure_small(size_t bytes);
     hipError_t ensure_colvec(size_t bytes);
     hipError_t ensure_pinned(size_t bytes);
@@ -159,9 +162,15 @@ template <typename T>
 hipError_t cg_spmm(const DevCsr<T> &M, const T *p, T *q, int64_t ld, int k, T *part, int *nparts,
                    const int *flags, hipStream_t st);
 
+// Device gates: the launches below that take `const int *go` do nothing
+// when go != nullptr and *go == 0 (a flag written by an earlier kernel on the
+// stream), so that a host-enqueued sequence can skip work decided on the GPU.
+
 // C (m x k, row-major, ldc) = X^T diag(d) Y with X given as segments.
 hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
-                int64_t ldc, Workspace &ws, hipStream_t st);
+                int64_t ldc, Workspace &ws, hipStream_t st, const int *go = nullptr);
+// Bytes of per-chunk partials gram() needs at most, for any shape.
+size_t gram_part_bytes_max();
 // The same product with the per-chunk partial tiles in the caller's device
 // buffer part (part_bytes): when it holds fewer chunks than gram() would use,
 // each work-group takes a longer chunk of rows (the summation order then
@@ -169,17 +178,84 @@ hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, c
 // partials used, and a null part only plans (nothing is launched).
 // hipErrorInvalidValue when not even one chunk fits or X has too many tiles.
 hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
-                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st);
+                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st,
+                     const int *go = nullptr);
 
 // Y = alpha * X S + beta * Y; X segments (m = total columns), S device row-major
 // (m x lds), Y n x k.
 hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
-                double *Y, int64_t ldy, hipStream_t st);
+                double *Y, int64_t ldy, hipStream_t st, const int *go = nullptr);
 
 // Y[:, j] = scale[j] * X[:, j] (scale == nullptr: copy) with type conversion.
 template <typename TI, typename TO>
 hipError_t copy_cols(int64_t n, int k, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const double *scale,
+                     hipStream_t st, const int *go = nullptr);
+
+// ------------------------------------------------ STEP 2 decisions on the device
+// The pass loops of Algorithm 3 (and of Algorithm 2 and the deflation against
+// [X, P]) are enqueued in full by the host; their "repeat until small" tests
+// and the drop decisions run on the device and gate the later launches, so
+// STEP 2 needs no host round trip until the kept count at its end.  A dropped
+// direction becomes a zero column in place; orth_finish moves the kept
+// columns to the front once.
+//
+// Flag layout (ints): [0] kept count, [1] nonzero once a direction was
+// dropped, [ORTH_ALIVE + j] column j alive (j < k), then one (go, upd) pair
+// per pass loop: go = the loop's next pass runs, upd = the current pass's
+// update is applied.
+constexpr int ORTH_ALIVE = 4;
+inline int *orth_loop(int *ints, int k, int loop) { return ints + ORTH_ALIVE + k + 2 * loop; }
+// kept = 0, dropped = 0, alive[j] = 1, every loop's go = upd = 1.
+hipError_t orth_init(int *ints, int k, int nloops, hipStream_t st);
+// scale[j] = 1 / sqrt(G[j][j]) for alive columns with G[j][j] > thr (finite),
+// else 0 and the column is marked dead (dropped set if it was alive).  Skipped
+// when go != nullptr and *go == 0 (scale is then left as is; callers gate the
+// scaling with the same flag).
+hipError_t orth_norm_scale(const double *G, int ldg, int k, double thr, int *ints, double *scale, const int *go,
+                           hipStream_t st);
+// The stopping test of a pass on its coefficient block R (rows x cols, ldr):
+// small = max |R| <= tol.  loop[1] (upd) = !(allow_skip && small); loop[0]
+// (go) = 0 when allow_break && small.  When loop[0] is already 0 the pass is
+// off: upd = 0.
+hipError_t orth_pass_test(const double *R, int rows, int cols, int ldr, double tol, int allow_skip, int allow_break,
+                          int *loop, hipStream_t st);
+// One leaf pass of Algorithm 3 (one work-group): Jacobi eigendecomposition
+// M = Q Lam Q^T of the leaf Gram (kl <= 16, ldm = kl), directions with
+// Lam <= drop_tol (or not finite) dropped, S (kl x kl, lds = kl) = the kept
+// columns of Q Lam^{-1/2} in ascending order of Lam, zero columns after them;
+// alive flags of the leaf's columns (alive = ints + ORTH_ALIVE + s) set to the
+// first kk; dev = max |Lam - 1| over the kept.  upd = 0 and go = 0 when
+// skip_final and nothing was dropped and dev <= orth_tol; else upd = 1 and
+// go = 0 when dev <= orth_tol or kk = 0.  Off (upd = 0) when go was 0.
+hipError_t orth_leaf(const double *M, int kl, double drop_tol, double orth_tol, int skip_final, int *ints, int s,
+                     double *S, int *loop, hipStream_t st);
+// Algorithm 2, one column w against the kept columns U of its block:
+// c = [U, w]^T B w (nu + 1 entries); state[0] = c[nu] on pass 0 (the squared
+// B-norm before the projection), state[1] = c[nu] - sum_{i<nu} c_i^2 (after it).
+hipError_t orth_mbo_coef(const double *c, int nu, int pass, double *state, hipStream_t st);
+// keep = state[0] > 0, state[1] finite and > drop_tol: scale = 1/sqrt(state[1])
+// or 0 with the column marked dead.
+hipError_t orth_mbo_keep(const double *state, double drop_tol, int *ints, int j, double *scale, hipStream_t st);
+// ints[0] = number of alive columns; when a direction was dropped, the alive
+// columns of W (n x k, ldw) move to the front in order, in place.
+hipError_t orth_finish(int64_t n, double *W, int64_t ldw, int k, int *ints, hipStream_t st);
+
+// ------------------------------- STEP 5 and the STEP 3 assembly on the device
+// ptilde (dim x nn, ld nn) = columns shift .. shift+nn-1 of xhat (dim x nx,
+// ld nx) with rows 0 .. n_old-1 zeroed (eq. CP_tilde); nrm0[j] = its column norms.
+hipError_t phat_init(int dim, int nx, const double *xhat, int shift, int n_old, int nn, double *pt, double *nrm0,
                      hipStream_t st);
+// Gram-Schmidt (twice) among the columns of pt, dropping those whose norm falls
+// to drop_tol * nrm0[j] or below: phat (dim x n_new, ld n_new) holds the kept
+// columns first and zeros after them; *np (device) their count.  dim <= 16384,
+// nn <= n_new <= 128.
+hipError_t phat_mgs(int dim, int nn, const double *pt, const double *nrm0, double drop_tol, double *phat, int n_new,
+                    int *np, hipStream_t st);
+// The structured Abar (dim x dim, ld dim) of Section 3.2 from lam (nx Ritz
+// values), alpha0 (np x np block of a0, ld lda0, symmetrized) and
+// G = [X_u, P, W]^T A W (dim x nw, ld nw).
+hipError_t assemble_abar(int dim, int nx, int np, int nw, const double *lam, const double *a0, int lda0,
+                         const double *G, double *Ab, hipStream_t st);
 
 // Move columns [src, src+cnt) to [dst, dst+cnt), dst < src, in place.
 hipError_t shift_cols_left(int64_t n, double *X, int64_t ld, int dst, int src, int cnt, hipStream_t st);
@@ -195,6 +271,12 @@ hipError_t fill_random(int64_t n, int k, int col0, uint64_t seed, double *X, int
 // m = a, then m[dpos[i]] -= theta * dg[i] when dg != nullptr); m32 = float(m).
 hipError_t shift_values(int64_t nnz, const double *a, const double *b, int64_t n, const int32_t *dpos,
                         const double *dg, double theta, double *m, float *m32, hipStream_t st);
+
+// *out = the first row i whose B diagonal is missing, not positive or not
+// finite: dg[i] (dg != nullptr, diagonal B) or b[dpos[i]] (CSR B on the union
+// pattern, dpos[i] < 0 when the row stores no diagonal); n when there is none.
+hipError_t first_nonpositive_diag(int64_t n, const int32_t *dpos, const double *b, const double *dg, int *out,
+                                  hipStream_t st);
 
 // gval[e] = sum_i w[i] X[r_e, i] X[c_e, i].
 hipError_t pattern_grad(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *X, int64_t ldx,

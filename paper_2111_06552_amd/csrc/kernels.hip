@@ -1176,10 +1176,12 @@ struct GramParams {
     double *part;
     int nchunk;
     int64_t rows_per;
+    const int *go;   // device flag: nothing is done when go != nullptr and *go == 0
 };
 
 template <int MB, int NB, int NS = MB == 1 ? 1 : 2>   // NS MFMA steps (4 rows each) per group
 __global__ __launch_bounds__(256) void k_gram(GramParams P) {
+    if (P.go != nullptr && *P.go == 0) return;
     constexpr int TM = 16 * MB, TN = 16 * NB;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int per_chunk = P.ntile * P.nyt;
@@ -1279,6 +1281,7 @@ __global__ __launch_bounds__(256) void k_gram(GramParams P) {
 // in range order.  The order depends only on nchunk, so results are
 // reproducible.
 __global__ __launch_bounds__(1024) void k_tile_reduce(GramParams P, int TN, int TE, double *C, int64_t ldc) {
+    if (P.go != nullptr && *P.go == 0) return;
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int epb = (TE + 63) / 64;
     const int tp = blockIdx.x / epb, e = (blockIdx.x % epb) * 64 + lane;
@@ -1315,6 +1318,7 @@ __global__ __launch_bounds__(1024) void k_tile_reduce(GramParams P, int TN, int 
 // its partial tile; k_tile_reduce sums the partials.
 template <bool HAS_D>
 __global__ __launch_bounds__(512) void k_gram_lds(GramParams P) {
+    if (P.go != nullptr && *P.go == 0) return;
     constexpr int T = 64, KR = 32, NT = 512;
     __shared__ double sbuf[2 * KR * T];   // X and Y stages; at the end, one wave group's tile
     double(*Xs)[T] = reinterpret_cast<double(*)[T]>(sbuf);
@@ -1411,7 +1415,7 @@ __global__ __launch_bounds__(512) void k_gram_lds(GramParams P) {
 }
 
 hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
-                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st) {
+                     int64_t ldc, double *part, size_t part_bytes, size_t *need, hipStream_t st, const int *go) {
     if (need) *need = 0;
     const int m = X.total();
     if (m == 0 || k == 0) return hipSuccess;
@@ -1458,6 +1462,7 @@ hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int
     }
     if (part == nullptr) return hipErrorInvalidValue;
     P.part = part;
+    P.go = go;
     dim3 grid(tiles * nchunk), block(256);
     if (lds) {
         if (d != nullptr) hipLaunchKernelGGL(k_gram_lds<true>, grid, dim3(512), 0, st, P);
@@ -1476,14 +1481,23 @@ hipError_t gram_into(int64_t n, const Segs &X, const double *Y, int64_t ldy, int
     return hipGetLastError();
 }
 
+// gram_into keeps tiles * chunks within one residency wave of the large-tile
+// kernel (64 x 64 tiles) or within 2048 work-groups of the small ones (at
+// most 32 x 32 tiles).
+size_t gram_part_bytes_max() {
+    const size_t lds = (size_t)resident_grid((const void *)k_gram_lds<false>, 1 << 30, 512) * 64 * 64 * sizeof(double);
+    const size_t small = (size_t)2048 * 32 * 32 * sizeof(double);
+    return std::max(lds, small);
+}
+
 hipError_t gram(int64_t n, const Segs &X, const double *Y, int64_t ldy, int k, const double *d, double *C,
-                int64_t ldc, Workspace &ws, hipStream_t st) {
+                int64_t ldc, Workspace &ws, hipStream_t st, const int *go) {
     size_t need = 0;
     hipError_t e = gram_into(n, X, Y, ldy, k, d, C, ldc, nullptr, SIZE_MAX, &need, st);
     if (e != hipSuccess || need == 0) return e;
     e = ws.ensure_part(need);
     if (e != hipSuccess) return e;
-    return gram_into(n, X, Y, ldy, k, d, C, ldc, ws.part, ws.part_bytes, nullptr, st);
+    return gram_into(n, X, Y, ldy, k, d, C, ldc, ws.part, ws.part_bytes, nullptr, st, go);
 }
 
 // ---------------------------------------------------------------------------
@@ -1502,6 +1516,7 @@ struct GemmParams {
     double *Y;
     int64_t ldy;
     int nct;
+    const int *go;   // device flag: nothing is done when go != nullptr and *go == 0
 };
 
 // BM x BN output tile per work-group, WM x WN waves of (BM/WM) x (BN/WN);
@@ -1510,6 +1525,7 @@ struct GemmParams {
 // branches) while the MFMAs consume the current chunk from LDS.
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmParams P) {
+    if (P.go != nullptr && *P.go == 0) return;
     constexpr int T = 64 * WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN, MB = TM / 16, NB = TN / 16;
     constexpr int VPT = BM * BK / T, SPT = BK * BN / T;
@@ -1605,9 +1621,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmParams P) {
 // column l; the input row is broadcast across the group by shuffles and S is
 // read from LDS.  Each row depends only on itself, so Y may alias X.
 template <int G>
-__global__ __launch_bounds__(256) void k_gemm_rows(int64_t n, const double *__restrict__ X, int64_t ldx, int m,
+__global__ __launch_bounds__(256) void k_gemm_rows(int64_t n, const double *X, int64_t ldx, int m,
                                                    const double *__restrict__ S, int64_t lds, int k, double alpha,
-                                                   double beta, double *Y, int64_t ldy) {
+                                                   double beta, double *Y, int64_t ldy, const int *go) {
+    if (go != nullptr && *go == 0) return;
     __shared__ double Ss[32 * 32];
     for (int i = threadIdx.x; i < m * k; i += 256) Ss[i] = S[(int64_t)(i / k) * lds + i % k];
     __syncthreads();
@@ -1665,9 +1682,10 @@ __device__ __forceinline__ void row_bcast_fma(double (&xv)[RU], const double (&s
     }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_rows16(int64_t n, const double *__restrict__ X, int64_t ldx, int m,
+__global__ __launch_bounds__(256) void k_gemm_rows16(int64_t n, const double *X, int64_t ldx, int m,
                                                      const double *__restrict__ S, int64_t lds, int k, double alpha,
-                                                     double beta, double *Y, int64_t ldy) {
+                                                     double beta, double *Y, int64_t ldy, const int *go) {
+    if (go != nullptr && *go == 0) return;
     constexpr int NGR = 16, RU = 4;   // 16 row groups of 16 lanes; RU rows per group and step
     const int grp = threadIdx.x / 16, l = threadIdx.x % 16;
     const int lx = l < m ? l : 0, ly = l < k ? l : 0;   // clamped columns: loads carry no branch
@@ -1704,7 +1722,7 @@ __global__ __launch_bounds__(256) void k_gemm_rows16(int64_t n, const double *__
 }
 
 hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, double alpha, double beta,
-                double *Y, int64_t ldy, hipStream_t st) {
+                double *Y, int64_t ldy, hipStream_t st, const int *go) {
     if (n == 0 || k == 0) return hipSuccess;
     if (X.nseg == 1 && X.s[0].ncol <= 32 && k <= 32) {
         const int m = X.s[0].ncol, w = std::max(m, k);
@@ -1713,10 +1731,10 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
         const int64_t nb = std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, (int64_t)num_cu() * 16);
         if (G == 16)
             hipLaunchKernelGGL(k_gemm_rows16, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, S, lds,
-                               k, alpha, beta, Y, ldy);
+                               k, alpha, beta, Y, ldy, go);
 #define GCGE_GR(Gv)                                                                                          \
     if (G == Gv) hipLaunchKernelGGL(k_gemm_rows<Gv>, dim3((unsigned)nb), dim3(256), 0, st, n, X.s[0].p, X.s[0].ld, m, \
-                                    S, lds, k, alpha, beta, Y, ldy);
+                                    S, lds, k, alpha, beta, Y, ldy, go);
         GCGE_GR(8) GCGE_GR(32)
 #undef GCGE_GR
         return hipGetLastError();
@@ -1737,6 +1755,7 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
     P.beta = beta;
     P.Y = Y;
     P.ldy = ldy;
+    P.go = go;
     // up to 64 output columns: 128 x 64 tiles, K chunks of 32, 4 waves;
     // wider: 128 x 128 tiles, K chunks of 16, 8 waves (4 x 2)
     const int BN = (k <= 64) ? 64 : 128;
@@ -1750,11 +1769,458 @@ hipError_t gemm(int64_t n, const Segs &X, const double *S, int64_t lds, int k, d
 }
 
 // ---------------------------------------------------------------------------
+// STEP 2 decisions on the device: the "repeat until small" tests and the drop
+// decisions of Algorithms 2 and 3, written to flags that gate the launches the
+// host has already enqueued (one work-group each; the blocks are small).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_orth_init(int *ints, int k, int nloops) {
+    const int total = ORTH_ALIVE + k + 2 * nloops;
+    for (int i = threadIdx.x; i < total; i += 256) ints[i] = (i < 2) ? 0 : 1;
+}
+
+hipError_t orth_init(int *ints, int k, int nloops, hipStream_t st) {
+    hipLaunchKernelGGL(k_orth_init, dim3(1), dim3(256), 0, st, ints, k, nloops);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(128) void k_orth_norm_scale(const double *__restrict__ G, int ldg, int k, double thr,
+                                                         int *ints, double *scale, const int *go) {
+    if (go != nullptr && *go == 0) return;
+    for (int j = threadIdx.x; j < k; j += 128) {
+        const double nu2 = G[(int64_t)j * ldg + j];
+        int *alive = ints + ORTH_ALIVE + j;
+        const bool keep = *alive != 0 && nu2 > thr && isfinite(nu2);
+        scale[j] = keep ? 1.0 / sqrt(nu2) : 0.0;
+        if (*alive && !keep) {
+            *alive = 0;
+            ints[1] = 1;
+        }
+    }
+}
+
+hipError_t orth_norm_scale(const double *G, int ldg, int k, double thr, int *ints, double *scale, const int *go,
+                           hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_orth_norm_scale, dim3(1), dim3(128), 0, st, G, ldg, k, thr, ints, scale, go);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_orth_pass_test(const double *__restrict__ R, int rows, int cols, int ldr,
+                                                        double tol, int allow_skip, int allow_break, int *loop) {
+    __shared__ double red[256];
+    if (loop[0] == 0) {
+        if (threadIdx.x == 0) loop[1] = 0;
+        return;
+    }
+    double m = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += 256) {
+        const double v = fabs(R[(e / cols) * ldr + e % cols]);
+        m = (v > m || v != v) ? v : m;   // a NaN makes the block "not small"
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + h];
+            red[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool small = red[0] <= tol;
+        loop[1] = (allow_skip && small) ? 0 : 1;
+        if (allow_break && small) loop[0] = 0;
+    }
+}
+
+hipError_t orth_pass_test(const double *R, int rows, int cols, int ldr, double tol, int allow_skip, int allow_break,
+                          int *loop, hipStream_t st) {
+    hipLaunchKernelGGL(k_orth_pass_test, dim3(1), dim3(256), 0, st, R, rows, cols, ldr, tol, allow_skip, allow_break,
+                       loop);
+    return hipGetLastError();
+}
+
+// Leaf pass of Algorithm 3 in one wave.  The symmetric kl x kl Gram is
+// diagonalized by cyclic Jacobi rotations (Golub & Van Loan, "Matrix
+// Computations", section 8.5): a rotation in the (p, q) plane with
+// tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1 / sqrt(1 + t^2), s = t c annihilates a_pq.  The pairs of one round
+// are a perfect matching of the indices (round-robin tournament, index 0
+// fixed, the others rotating), so their rotations commute: all row updates,
+// then all column updates (and the eigenvector updates V <- V J).  A rotation
+// is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|); the sweeps end after one
+// with no rotation.
+constexpr int LEAF_MAX = 16;
+__device__ __forceinline__ int rr_player(int pos, int round, int np) {
+    return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
+}
+
+__global__ __launch_bounds__(64) void k_orth_leaf(const double *__restrict__ M, int kl, double drop_tol,
+                                                  double orth_tol, int skip_final, int *ints, int s0, double *S,
+                                                  int *loop) {
+    constexpr int L = LEAF_MAX;
+    __shared__ double a[L][L + 1], v[L][L + 1];
+    __shared__ double cs[L / 2], sn[L / 2];
+    __shared__ int pp[L / 2], qq[L / 2];
+    __shared__ int rot;
+    __shared__ double lam[L];
+    __shared__ int rank[L];
+    const int t = threadIdx.x;
+    if (loop[0] == 0) {
+        if (t == 0) loop[1] = 0;
+        return;
+    }
+    for (int e = t; e < L * L; e += 64) {
+        const int i = e / L, j = e % L;
+        a[i][j] = (i < kl && j < kl) ? 0.5 * (M[i * kl + j] + M[j * kl + i]) : 0.0;
+        v[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int np = (kl + 1) & ~1;   // an odd kl plays against a dummy index kl
+    const int npair = np / 2;
+    const double eps = 2.220446049250313e-16;
+    for (int sweep = 0; sweep < 50 && kl > 1; ++sweep) {
+        if (t == 0) rot = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            if (t < npair) {
+                int p = rr_player(t, round, np), q = rr_player(np - 1 - t, round, np);
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                double c = 1.0, sv = 0.0;
+                if (q < kl) {
+                    const double apq = a[p][q], app = a[p][p], aqq = a[q][q];
+                    if (apq != 0.0 && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        sv = tt * c;
+                        rot = 1;
+                    }
+                }
+                pp[t] = p;
+                qq[t] = q < kl ? q : -1;
+                cs[t] = c;
+                sn[t] = sv;
+            }
+            __syncthreads();
+            for (int e = t; e < npair * L; e += 64) {   // rows p, q of J^T A
+                const int i = e / L, j = e % L, p = pp[i], q = qq[i];
+                if (q < 0 || j >= kl) continue;
+                const double x = a[p][j], y = a[q][j];
+                a[p][j] = cs[i] * x - sn[i] * y;
+                a[q][j] = sn[i] * x + cs[i] * y;
+            }
+            __syncthreads();
+            for (int e = t; e < npair * L; e += 64) {   // columns p, q of (J^T A) J and of V J
+                const int i = e / L, j = e % L, p = pp[i], q = qq[i];
+                if (q < 0 || j >= kl) continue;
+                const double x = a[j][p], y = a[j][q];
+                a[j][p] = cs[i] * x - sn[i] * y;
+                a[j][q] = sn[i] * x + cs[i] * y;
+                const double xv = v[j][p], yv = v[j][q];
+                v[j][p] = cs[i] * xv - sn[i] * yv;
+                v[j][q] = sn[i] * xv + cs[i] * yv;
+            }
+            __syncthreads();
+        }
+        if (rot == 0) break;
+        __syncthreads();
+    }
+    // eigenvalues, their ascending order (ties by index) and the drop test
+    int *alive = ints + ORTH_ALIVE + s0;
+    if (t < kl) lam[t] = a[t][t];
+    __syncthreads();
+    if (t < kl) {
+        int r = 0;
+        for (int i = 0; i < kl; ++i) r += (lam[i] < lam[t] || (lam[i] == lam[t] && i < t)) ? 1 : 0;
+        rank[r] = t;   // rank[r] = index of the r-th smallest eigenvalue
+    }
+    __syncthreads();
+    if (t == 0) {
+        int kk = 0, nz = 0;
+        double dev = 0.0;
+        for (int r = 0; r < kl; ++r) {
+            const double l = lam[rank[r]];
+            if (l > drop_tol && isfinite(l)) {
+                ++kk;
+                dev = fmax(dev, fabs(l - 1.0));
+            }
+        }
+        for (int j = 0; j < kl; ++j) nz += alive[j] != 0;
+        rot = kk;   // reuse: number kept
+        const bool skip = skip_final && kk == nz && dev <= orth_tol;
+        loop[1] = skip ? 0 : 1;
+        if (skip || dev <= orth_tol || kk == 0) loop[0] = 0;
+        if (!skip) {
+            if (kk < nz) ints[1] = 1;
+            for (int j = 0; j < kl; ++j) alive[j] = j < kk ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    // S[:, col] = Q[:, j] / sqrt(lam_j) for the kept j in ascending order, zero after
+    if (loop[1] != 0) {
+        for (int e = t; e < kl * kl; e += 64) {
+            const int i = e / kl, col = e % kl;
+            double val = 0.0;
+            if (col < rot) {
+                // the col-th kept eigenvalue in ascending order
+                int seen = 0, j = -1;
+                for (int r = 0; r < kl; ++r) {
+                    const double l = lam[rank[r]];
+                    if (l > drop_tol && isfinite(l)) {
+                        if (seen == col) {
+                            j = rank[r];
+                            break;
+                        }
+                        ++seen;
+                    }
+                }
+                val = v[i][j] / sqrt(lam[j]);
+            }
+            S[i * kl + col] = val;
+        }
+    }
+}
+
+hipError_t orth_leaf(const double *M, int kl, double drop_tol, double orth_tol, int skip_final, int *ints, int s,
+                     double *S, int *loop, hipStream_t st) {
+    if (kl < 1 || kl > LEAF_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_orth_leaf, dim3(1), dim3(64), 0, st, M, kl, drop_tol, orth_tol, skip_final, ints, s, S,
+                       loop);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_orth_mbo_coef(const double *__restrict__ c, int nu, int pass,
+                                                       double *state) {
+    __shared__ double red[256];
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < nu; i += 256) ss += c[i] * c[i];
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (pass == 0) state[0] = c[nu];
+        state[1] = c[nu] - red[0];
+    }
+}
+
+hipError_t orth_mbo_coef(const double *c, int nu, int pass, double *state, hipStream_t st) {
+    hipLaunchKernelGGL(k_orth_mbo_coef, dim3(1), dim3(256), 0, st, c, nu, pass, state);
+    return hipGetLastError();
+}
+
+__global__ void k_orth_mbo_keep(const double *__restrict__ state, double drop_tol, int *ints, int j, double *scale) {
+    if (threadIdx.x != 0) return;
+    const double n0 = state[0], n1 = state[1];
+    const bool keep = ints[ORTH_ALIVE + j] != 0 && n0 > 0.0 && isfinite(n1) && n1 > drop_tol;
+    scale[0] = keep ? 1.0 / sqrt(n1) : 0.0;
+    if (ints[ORTH_ALIVE + j] && !keep) {
+        ints[ORTH_ALIVE + j] = 0;
+        ints[1] = 1;
+    }
+}
+
+hipError_t orth_mbo_keep(const double *state, double drop_tol, int *ints, int j, double *scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_orth_mbo_keep, dim3(1), dim3(64), 0, st, state, drop_tol, ints, j, scale);
+    return hipGetLastError();
+}
+
+// Kept count, and (only when something was dropped) the in-place compaction
+// of every row: one wave per row walks the row in chunks of 64 columns, in
+// order.  A kept column j moves to pos[j] <= j, a position that the wave has
+// already read (in an earlier chunk, or in this chunk, whose loads all come
+// before its stores), and a row belongs to one wave, so the move is safe in
+// place.  The column map is built in LDS by each work-group.
+constexpr int ORTH_FINISH_MAXK = 4096;
+__global__ __launch_bounds__(256) void k_orth_finish(int64_t n, double *W, int64_t ldw, int k, int *ints) {
+    __shared__ int pos[ORTH_FINISH_MAXK];
+    __shared__ int kept;
+    const int *alive = ints + ORTH_ALIVE;
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int j = 0; j < k; ++j) {
+            pos[j] = alive[j] ? c : -1;
+            c += alive[j] != 0;
+        }
+        kept = c;
+        if (blockIdx.x == 0) ints[0] = c;
+    }
+    __syncthreads();
+    if (ints[1] == 0 || kept == k) return;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wave; row < n; row += (int64_t)gridDim.x * 4) {
+        double *w = W + row * ldw;
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            const int j = c0 + lane;
+            const double v = j < k ? w[j] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            if (j < k && pos[j] >= 0) w[pos[j]] = v;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+hipError_t orth_finish(int64_t n, double *W, int64_t ldw, int k, int *ints, hipStream_t st) {
+    if (k > ORTH_FINISH_MAXK) return hipErrorInvalidValue;
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, (int64_t)num_cu() * 8));
+    hipLaunchKernelGGL(k_orth_finish, dim3((unsigned)nb), dim3(256), 0, st, n, W, ldw, k, ints);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// STEP 5 and the STEP 3 assembly on the device (the Rayleigh-Ritz quantities
+// stay in device memory: xhat, Abar, phat, alpha0).
+// ---------------------------------------------------------------------------
+// ptilde = columns shift .. shift + nn - 1 of xhat (dim x nx, ld nx) with rows
+// 0 .. n_old - 1 zeroed (eq. CP_tilde), and the norm of each of its columns.
+// One work-group per column.
+__global__ __launch_bounds__(256) void k_phat_init(int dim, int nx, const double *__restrict__ xhat, int shift,
+                                                   int n_old, int nn, double *__restrict__ pt,
+                                                   double *__restrict__ nrm0) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < dim; i += 256) {
+        const double v = i < n_old ? 0.0 : xhat[(int64_t)i * nx + shift + j];
+        pt[(int64_t)i * nn + j] = v;
+        ss += v * v;
+    }
+    red[threadIdx.x] = ss;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nrm0[j] = sqrt(red[0]);
+}
+
+hipError_t phat_init(int dim, int nx, const double *xhat, int shift, int n_old, int nn, double *pt, double *nrm0,
+                     hipStream_t st) {
+    if (nn <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_phat_init, dim3(nn), dim3(256), 0, st, dim, nx, xhat, shift, n_old, nn, pt, nrm0);
+    return hipGetLastError();
+}
+
+// Gram-Schmidt among the columns of pt (dim x nn, ld nn) in one work-group:
+// column j is orthogonalized against the columns kept so far (twice; each
+// pass takes all coefficients against the kept columns at once), then kept
+// (normalized, at the next free column of phat) when its norm exceeds
+// drop_tol times its norm before the projections against xhat, nrm0[j].
+// Columns of phat (dim x n_new, ld n_new) past the kept ones are zeroed; *np
+// receives the kept count.  The column being processed sits in LDS (dim
+// doubles, dynamic), the kept columns in phat (global, cache-resident).
+constexpr int PHAT_MAXDIM = 16384, PHAT_T = 1024;
+__global__ __launch_bounds__(PHAT_T) void k_phat_mgs(int dim, int nn, const double *__restrict__ pt,
+                                                     const double *__restrict__ nrm0, double drop_tol,
+                                                     double *__restrict__ phat, int n_new, int *np_out) {
+    extern __shared__ double v[];
+    __shared__ double cf[128];
+    __shared__ double red[PHAT_T / 64];
+    __shared__ int s_np;
+    const int t = threadIdx.x, wave = t / 64, lane = t % 64, nw = PHAT_T / 64;
+    if (t == 0) s_np = 0;
+    __syncthreads();
+    for (int j = 0; j < nn; ++j) {
+        for (int i = t; i < dim; i += PHAT_T) v[i] = pt[(int64_t)i * nn + j];
+        __syncthreads();
+        const int np = s_np;
+        for (int pass = 0; pass < 2 && np > 0; ++pass) {
+            for (int q = wave; q < np; q += nw) {   // cf[q] = phat[:, q] . v, one wave per coefficient
+                double s = 0.0;
+                for (int i = lane; i < dim; i += 64) s += phat[(int64_t)i * n_new + q] * v[i];
+                s = wave_sum(s);
+                if (lane == 0) cf[q] = s;
+            }
+            __syncthreads();
+            for (int i = t; i < dim; i += PHAT_T) {
+                double x = v[i];
+                for (int q = 0; q < np; ++q) x -= cf[q] * phat[(int64_t)i * n_new + q];
+                v[i] = x;
+            }
+            __syncthreads();
+        }
+        double s = 0.0;
+        for (int i = t; i < dim; i += PHAT_T) s += v[i] * v[i];
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        double nrm = 0.0;
+        for (int w = 0; w < nw; ++w) nrm += red[w];
+        nrm = sqrt(nrm);
+        const bool keep = nrm0[j] > 0.0 && nrm > drop_tol * nrm0[j];
+        if (keep)
+            for (int i = t; i < dim; i += PHAT_T) phat[(int64_t)i * n_new + np] = v[i] / nrm;
+        __syncthreads();
+        if (t == 0 && keep) s_np = np + 1;
+        __syncthreads();
+    }
+    const int np = s_np;
+    for (int e = t; e < dim * (n_new - np); e += PHAT_T) {
+        const int i = e / (n_new - np), q = np + e % (n_new - np);
+        phat[(int64_t)i * n_new + q] = 0.0;
+    }
+    if (t == 0) np_out[0] = np;
+}
+
+hipError_t phat_mgs(int dim, int nn, const double *pt, const double *nrm0, double drop_tol, double *phat, int n_new,
+                    int *np, hipStream_t st) {
+    if (dim > PHAT_MAXDIM || nn > 128 || n_new > 128 || nn > n_new) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_phat_mgs, dim3(1), dim3(PHAT_T), sizeof(double) * dim, st, dim, nn, pt, nrm0, drop_tol, phat,
+                       n_new, np);
+    return hipGetLastError();
+}
+
+// Abar over V_u = [X_u, P, W] (dim = nx + np + nw) with the structure of
+// Section 3.2: X_u^T A X_u = diag(lam), X_u^T A P = 0, P^T A P = alpha0
+// (symmetrized), and the last block column [X_u, P, W]^T A W = G (dim x nw,
+// ld nw), mirrored below the diagonal, its W block symmetrized.
+__global__ __launch_bounds__(256) void k_assemble_abar(int dim, int nx, int np, int nw, const double *__restrict__ lam,
+                                                       const double *__restrict__ a0, int lda0,
+                                                       const double *__restrict__ G, double *__restrict__ Ab) {
+    const int64_t total = (int64_t)dim * dim;
+    const int wb = nx + np;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e / dim), j = (int)(e % dim);
+        double v = 0.0;
+        if (i >= wb && j >= wb) {
+            v = 0.5 * (G[(int64_t)i * nw + (j - wb)] + G[(int64_t)j * nw + (i - wb)]);
+        } else if (j >= wb) {
+            v = G[(int64_t)i * nw + (j - wb)];
+        } else if (i >= wb) {
+            v = G[(int64_t)j * nw + (i - wb)];
+        } else if (i < nx && j < nx) {
+            v = (i == j) ? lam[i] : 0.0;
+        } else if (i >= nx && j >= nx) {
+            const int a = i - nx, b = j - nx;
+            v = 0.5 * (a0[(int64_t)a * lda0 + b] + a0[(int64_t)b * lda0 + a]);
+        }
+        Ab[e] = v;
+    }
+}
+
+hipError_t assemble_abar(int dim, int nx, int np, int nw, const double *lam, const double *a0, int lda0,
+                         const double *G, double *Ab, hipStream_t st) {
+    if (dim <= 0) return hipSuccess;
+    const int64_t total = (int64_t)dim * dim;
+    hipLaunchKernelGGL(k_assemble_abar, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0,
+                       st, dim, nx, np, nw, lam, a0, lda0, G, Ab);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // small elementwise kernels
 // ---------------------------------------------------------------------------
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_copy_cols(int64_t n, int k, const TI *__restrict__ X, int64_t ldx,
-                                                   TO *__restrict__ Y, int64_t ldy, const double *__restrict__ scale) {
+__global__ __launch_bounds__(256) void k_copy_cols(int64_t n, int k, const TI *X, int64_t ldx, TO *Y, int64_t ldy,
+                                                   const double *__restrict__ scale, const int *go) {
+    if (go != nullptr && *go == 0) return;
     const int64_t total = n * k;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
         const int64_t i = t / k;
@@ -1772,19 +2238,19 @@ static inline unsigned ew_grid(int64_t total) {
 
 template <typename TI, typename TO>
 hipError_t copy_cols(int64_t n, int k, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const double *scale,
-                     hipStream_t st) {
+                     hipStream_t st, const int *go) {
     if (n == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_copy_cols<TI, TO>), dim3(ew_grid(n * k)), dim3(256), 0, st, n, k, X, ldx, Y, ldy, scale);
+    hipLaunchKernelGGL((k_copy_cols<TI, TO>), dim3(ew_grid(n * k)), dim3(256), 0, st, n, k, X, ldx, Y, ldy, scale, go);
     return hipGetLastError();
 }
 template hipError_t copy_cols<double, double>(int64_t, int, const double *, int64_t, double *, int64_t,
-                                              const double *, hipStream_t);
+                                                const double *, hipStream_t, const int *);
 template hipError_t copy_cols<float, double>(int64_t, int, const float *, int64_t, double *, int64_t,
-                                             const double *, hipStream_t);
+                                                const double *, hipStream_t, const int *);
 template hipError_t copy_cols<double, float>(int64_t, int, const double *, int64_t, float *, int64_t,
-                                             const double *, hipStream_t);
+                                                const double *, hipStream_t, const int *);
 template hipError_t copy_cols<float, float>(int64_t, int, const float *, int64_t, float *, int64_t,
-                                            const double *, hipStream_t);
+                                                const double *, hipStream_t, const int *);
 
 // one thread per row; columns move left in increasing order, so a source is
 // always read before its slot is overwritten
@@ -1858,6 +2324,35 @@ __global__ __launch_bounds__(256) void k_shift_diag(int64_t n, const int32_t *__
                                                     const double *__restrict__ dg, double theta, double *m) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         m[dpos[i]] = fma(-theta, (dg != nullptr) ? dg[i] : 1.0, m[dpos[i]]);
+}
+
+// One work-group scans all rows (a one-off check at set-up) and keeps the
+// smallest offending row in LDS; thread 0 writes it.
+__global__ __launch_bounds__(1024) void k_first_bad_diag(int64_t n, const int32_t *__restrict__ dpos,
+                                                         const double *__restrict__ b, const double *__restrict__ dg,
+                                                         int *out) {
+    __shared__ int64_t lo[1024];
+    int64_t best = n;
+    for (int64_t i = threadIdx.x; i < n && i < best; i += 1024) {
+        double v;
+        if (dg != nullptr) v = dg[i];
+        else v = dpos[i] >= 0 ? b[dpos[i]] : 0.0;
+        if (!(v > 0.0) || !isfinite(v)) best = i;
+    }
+    lo[threadIdx.x] = best;
+    __syncthreads();
+    for (int h = 512; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (int)lo[0];
+}
+
+hipError_t first_nonpositive_diag(int64_t n, const int32_t *dpos, const double *b, const double *dg, int *out,
+                                  hipStream_t st) {
+    if (n > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_first_bad_diag, dim3(1), dim3(1024), 0, st, n, dpos, b, dg, out);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(int64_t nnz, const double *__restrict__ m, float *m32) {
@@ -1997,6 +2492,7 @@ static hipError_t grow(void **p, size_t *cap, size_t bytes) {
 }
 
 hipError_t Workspace::ensure_part(size_t bytes) { return grow((void **)&part, &part_bytes, bytes); }
+hipError_t Workspace::ensure_orth(size_t bytes) { return grow((void **)&orth, &orth_bytes, bytes); }
 hipError_t Workspace::ensure_small(size_t bytes) { return grow((void **)&small, &small_bytes, bytes); }
 hipError_t Workspace::ensure_colvec(size_t bytes) { return grow((void **)&colvec, &colvec_bytes, bytes); }
 hipError_t Workspace::ensure_flags() {

@@ -4,6 +4,7 @@
 #include "operator.h"
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <cmath>
 #include <cstring>
@@ -20,14 +21,16 @@ hipError_t scatter_values(int64_t nnz, const int32_t *map, const double *src, do
     } while (0)
 
 // ------------------------------------------------------------------ Stager
-// Waits for the stream by polling it: the host decisions of STEP 2 (leaf
-// eigensolves, pass tests) wait on a small download about twenty times per
-// iteration, and a blocking wait wakes up tens of microseconds after the copy
-// has finished.
+// Waits for the stream: polls it for up to 100 us (a short download is back
+// well before a blocking wait would wake up, tens of microseconds after the
+// copy), then blocks, so that a long phase (an inner CG solve) does not keep
+// a host core spinning.
 static hipError_t spin_wait(hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
         const hipError_t e = hipStreamQuery(st);
         if (e != hipErrorNotReady) return e;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(100)) return hipStreamSynchronize(st);
     }
 }
 
@@ -192,7 +195,7 @@ int Operator::build(const gcge_csr *A, int b_kind, const void *B, hipStream_t st
         if (!check_pattern(n, nnzB, brp, bci, err, "B")) return GCGE_ERR_INVALID_ARG;
     }
     // union pattern: A's entries, B's entries (CSR) or the diagonal (identity / diagonal B)
-    std::vector<int32_t> urp(n + 1), uci, ma(nnzA), mb(nnzB), dp(n);
+    std::vector<int32_t> urp(n + 1), uci, ma(nnzA), mb(nnzB), dp(n, -1);   // dp: -1 = no stored diagonal
     uci.reserve(nnzA + (Bc ? nnzB : n) / 8 + 16);
     urp[0] = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -236,10 +239,9 @@ int Operator::build(const gcge_csr *A, int b_kind, const void *B, hipStream_t st
     if (Bc) {
         GCGE_HIP(hipMalloc((void **)&mapB, sizeof(int32_t) * std::max<int64_t>(nnzB, 1)));
         if (nnzB) GCGE_HIP(hipMemcpy(mapB, mb.data(), sizeof(int32_t) * nnzB, hipMemcpyHostToDevice));
-    } else {
-        GCGE_HIP(hipMalloc((void **)&dpos, sizeof(int32_t) * n));
-        GCGE_HIP(hipMemcpy(dpos, dp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     }
+    GCGE_HIP(hipMalloc((void **)&dpos, sizeof(int32_t) * n));
+    GCGE_HIP(hipMemcpy(dpos, dp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     {
         const std::vector<int32_t> uo = spmm_unit_order(n, urp.data(), uci.data(), &plane);
         if (!uo.empty()) {
@@ -275,7 +277,29 @@ int Operator::set_values(const double *a_val, const void *b_val, hipStream_t st,
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         err = std::string("operator values: ") + hipGetErrorString(e);
-        return GCGE_ERR_HIP;
+        return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP;
+    }
+    return GCGE_OK;
+}
+
+int Operator::check_b_positive(hipStream_t st, std::string &err) const {
+    if (bkind == GCGE_B_IDENTITY) return GCGE_OK;
+    int bad = (int)n;
+    int *dbad = nullptr;
+    hipError_t e = hipMalloc((void **)&dbad, sizeof(int));
+    if (e == hipSuccess) e = first_nonpositive_diag(n, dpos, bkind == GCGE_B_CSR ? b : nullptr,
+                                                    bkind == GCGE_B_DIAG ? dg : nullptr, dbad, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (dbad) (void)hipFree(dbad);
+    if (e != hipSuccess) {
+        err = std::string("B check: ") + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP;
+    }
+    if (bad < n) {
+        err = "B is not positive definite: its diagonal entry in row " + std::to_string(bad) +
+              (bkind == GCGE_B_CSR ? " is missing, not positive or not finite" : " is not positive or not finite");
+        return GCGE_ERR_NOT_SPD;
     }
     return GCGE_OK;
 }
@@ -327,318 +351,178 @@ hipError_t Operator::residual(const double *X, int64_t ldx, int k, const double 
 // ------------------------------------------------------ orthogonalization
 namespace {
 
-struct OrthCtx {
+// STEP 2 as one enqueued sequence: every pass of every loop of the
+// deflation against [X, P] and of Algorithm 3 (or 2) is launched by the host
+// up front (at most max_pass per loop); the stopping tests and the drop
+// decisions run on the device and gate the later launches (orth_pass_test,
+// orth_leaf, orth_norm_scale write the flags; gram, gemm, copy_cols and the B
+// product read them).  A dropped direction becomes a zero column in place, so
+// every launch has a size known on the host; orth_finish moves the kept
+// columns to the front at the end, and the kept count is the one value the
+// host waits for.
+struct DevOrth {
     int64_t n;
     const BOp &B;
     double *W;
     int64_t ldw;
-    double *BW;   // CSR only
+    double *BW;   // CSR only: B W, kept in step with W
     int64_t ldbw;
+    int k;        // columns of W (fixed; dropped ones are zero)
     const OrthOptions &opt;
     Workspace &ws;
-    Stager &stg;
     hipStream_t st;
-    OrthStats *os;
     std::string &err;
-    int c;   // leaf size
+    int *ints = nullptr;        // device flags (layout in internal.h)
+    double *G = nullptr;        // k x k, and the mq x k coefficients against Q
+    double *Ml = nullptr;       // leaf Gram (<= 16 x 16)
+    double *Sl = nullptr;       // leaf transform (<= 16 x 16)
+    double *Rn = nullptr;       // node / block coefficients (<= k x k), Algorithm 2 column coefficients
+    double *scale = nullptr;    // per-column scales (k)
+    double *state = nullptr;    // Algorithm 2 norms (2)
+    int nloops = 0, next_loop = 0;
+    int grams = 0;
+    hipError_t e = hipSuccess;  // first launch error
 
     bool csr() const { return B.kind == GCGE_B_CSR; }
     const double *dweight() const { return B.kind == GCGE_B_DIAG ? B.dg : nullptr; }
-
-    int fail(hipError_t e, const char *what) {
-        err = std::string(what) + ": " + hipGetErrorString(e);
-        return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP;
+    int *loop(int i) { return orth_loop(ints, k, i); }
+    int new_loop() { return next_loop++; }
+    void chk(hipError_t r) {
+        if (e == hipSuccess) e = r;
     }
 
-    // C (host, m x k) = X^T Y with Y already B-applied (CSR) or weighted by d
-    int gram_host(const Segs &X, const double *Y, int64_t ldy, int k, bool yB, std::vector<double> &C) {
-        const int m = X.total();
-        C.assign((size_t)m * k, 0.0);
-        if (m == 0 || k == 0) return GCGE_OK;
-        hipError_t e = ws.ensure_small(sizeof(double) * ((size_t)m * k + 64));
-        if (e != hipSuccess) return fail(e, "workspace");
-        e = gram(n, X, Y, ldy, k, yB ? nullptr : dweight(), ws.small, k, ws, st);
-        if (e != hipSuccess) return fail(e, "gram");
-        e = stg.download(C.data(), ws.small, sizeof(double) * m * k);
-        if (e != hipSuccess) return fail(e, "download");
-        if (os) os->grams++;
-        return GCGE_OK;
-    }
-
-    // Y = alpha X S + beta Y with S host (m x k)
-    int gemm_host(const Segs &X, const std::vector<double> &S, int k, double alpha, double beta, double *Y,
-                  int64_t ldy) {
-        const int m = X.total();
-        if (m == 0 || k == 0) return GCGE_OK;
-        // S goes to the second half of the small workspace (the first half holds Gram results)
-        hipError_t e = ws.ensure_small(sizeof(double) * (2 * (size_t)m * k + 64));
-        if (e != hipSuccess) return fail(e, "workspace");
-        double *Sd = ws.small + (size_t)m * k + 32;
-        e = stg.upload(Sd, S.data(), sizeof(double) * m * k);
-        if (e != hipSuccess) return fail(e, "upload");
-        e = gemm(n, X, Sd, k, k, alpha, beta, Y, ldy, st);
-        if (e != hipSuccess) return fail(e, "gemm");
-        return GCGE_OK;
-    }
-
-    // B-norms of columns [s, s+k) (host)
-    int bnorms(int s, int k, std::vector<double> &nu) {
+    // C = X^T B Y for X = W (or BW for CSR when bx) columns [xs, xs + m) and
+    // Y = W columns [ys, ys + kk); ldc = kk
+    void gram_w(int xs, int m, int ys, int kk, double *C, const int *go) {
+        if (m <= 0 || kk <= 0) return;
         Segs X;
-        X.add(W + s, ldw, k);
-        std::vector<double> C;
-        int rc = csr() ? gram_host(X, BW + s, ldbw, k, true, C) : gram_host(X, W + s, ldw, k, false, C);
-        if (rc) return rc;
-        nu.resize(k);
-        for (int j = 0; j < k; ++j) nu[j] = std::sqrt(std::max(C[(size_t)j * k + j], 0.0));
-        return GCGE_OK;
+        if (csr()) X.add(BW + xs, ldbw, m);
+        else X.add(W + xs, ldw, m);
+        chk(gram(n, X, W + ys, ldw, kk, csr() ? nullptr : dweight(), C, kk, ws, st, go));
+        ++grams;
     }
-
-    int refresh_bw(int s, int k) {
-        if (!csr() || k == 0) return GCGE_OK;
-        hipError_t e = bop_apply(B, n, W + s, ldw, k, BW + s, ldbw, st);
-        return e == hipSuccess ? GCGE_OK : fail(e, "B W");
+    // the leaf / norm Gram X^T B X with Y = B X for CSR (X = W columns [s, s + m))
+    void gram_self(int s, int m, double *C, const int *go) {
+        Segs X;
+        X.add(W + s, ldw, m);
+        if (csr()) chk(gram(n, X, BW + s, ldbw, m, nullptr, C, m, ws, st, go));
+        else chk(gram(n, X, W + s, ldw, m, dweight(), C, m, ws, st, go));
+        ++grams;
     }
-
-    // keep the columns [s, s+k) with flag set, compacting them to the front
-    int compact(int s, int k, const std::vector<char> &keep, int *kept) {
-        int dst = 0;
-        int j = 0;
-        while (j < k) {
-            if (!keep[j]) {
-                ++j;
-                continue;
-            }
-            int j2 = j;
-            while (j2 < k && keep[j2]) ++j2;
-            if (dst != j) {
-                hipError_t e = shift_cols_left(n, W + s, ldw, dst, j, j2 - j, st);
-                if (e == hipSuccess && csr()) e = shift_cols_left(n, BW + s, ldbw, dst, j, j2 - j, st);
-                if (e != hipSuccess) return fail(e, "compact");
-            }
-            dst += j2 - j;
-            j = j2;
+    // W[:, ys..ys+kk) (and BW) = alpha W[:, xs..xs+m) S + beta (same)
+    void update(int xs, int m, const double *S, int64_t lds, int ys, int kk, double alpha, double beta,
+                const int *go) {
+        if (m <= 0 || kk <= 0) return;
+        Segs X;
+        X.add(W + xs, ldw, m);
+        chk(gemm(n, X, S, lds, kk, alpha, beta, W + ys, ldw, st, go));
+        if (csr()) {
+            Segs XB;
+            XB.add(BW + xs, ldbw, m);
+            chk(gemm(n, XB, S, lds, kk, alpha, beta, BW + ys, ldbw, st, go));
         }
-        *kept = dst;
-        if (os) os->dropped += k - dst;
-        return GCGE_OK;
     }
-
-    // scale columns [s, s+k) to unit B-norm, dropping those with nu^2 <= thr
-    int normalize(int s, int k, double thr, int *kept) {
-        std::vector<double> nu;
-        int rc = bnorms(s, k, nu);
-        if (rc) return rc;
-        std::vector<char> keep(k);
-        std::vector<double> sc(k);
-        for (int j = 0; j < k; ++j) {
-            keep[j] = nu[j] * nu[j] > thr && std::isfinite(nu[j]);
-            sc[j] = keep[j] ? 1.0 / nu[j] : 0.0;
+    // BW = B W for columns [0, k) (CSR only)
+    void refresh_bw(const int *go) {
+        if (!csr()) return;
+        for (int c0 = 0; c0 < k; c0 += 128) {
+            Affine<double> af;   // y = 0 - (-1) (B x)
+            af.ws = -1.0;
+            chk(spmm_affine<double>(B.csr, W + c0, ldw, std::min(128, k - c0), BW + c0, ldbw, af, st, nullptr, 0,
+                                    nullptr, nullptr, go));
         }
-        hipError_t e = ws.ensure_colvec(sizeof(double) * (k + 8));
-        if (e != hipSuccess) return fail(e, "workspace");
-        e = stg.upload(ws.colvec, sc.data(), sizeof(double) * k);
-        if (e == hipSuccess) e = copy_cols<double, double>(n, k, W + s, ldw, W + s, ldw, ws.colvec, st);
-        if (e == hipSuccess && csr()) e = copy_cols<double, double>(n, k, BW + s, ldbw, BW + s, ldbw, ws.colvec, st);
-        if (e != hipSuccess) return fail(e, "scale");
-        return compact(s, k, keep, kept);
+    }
+    // unit B-norm columns; those with squared norm <= thr are dropped
+    void normalize(double thr, const int *go) {
+        gram_self(0, k, G, go);
+        chk(orth_norm_scale(G, k, k, thr, ints, scale, go, st));
+        chk(copy_cols<double, double>(n, k, W, ldw, W, ldw, scale, st, go));
+        if (csr()) chk(copy_cols<double, double>(n, k, BW, ldbw, BW, ldbw, scale, st, go));
     }
 
-    // Algorithm 2 on columns [0, k): blocks of b consecutive columns; inside a
-    // block each column is B-orthogonalized against the block's kept columns
-    // by Gram-Schmidt (two passes, one reduction each: the coefficients and
-    // the column's own squared B-norm, the norm after the projection following
-    // by Pythagoras), normalized or dropped (squared B-norm ratio at most
-    // drop_tol), then the block's kept columns are deflated from all later
-    // columns (repeated until the coefficients are small).  Kept columns are
-    // moved to the front as they are accepted.
-    int mbo(int k, int b, int *kept) {
-        int out = 0, cur = 0;
-        hipError_t e = ws.ensure_colvec(sizeof(double) * 16);
-        if (e != hipSuccess) return fail(e, "workspace");
-        while (cur < k) {
+    // repeat R = Q^T B W, W -= Q R until small; after the first pass the
+    // columns that lay in span(Q) are dropped and the rest renormalized
+    void deflate(const Segs &Q) {
+        const int mq = Q.total();
+        const int L = new_loop();
+        for (int pass = 0; pass < opt.max_pass; ++pass) {
+            int *lp = loop(L);
+            chk(gram(n, Q, csr() ? BW : W, csr() ? ldbw : ldw, k, csr() ? nullptr : dweight(), G, k, ws, st, lp));
+            ++grams;
+            chk(orth_pass_test(G, mq, k, k, opt.orth_tol, opt.skip_final && pass > 0, pass > 0, lp, st));
+            chk(gemm(n, Q, G, k, k, -1.0, 1.0, W, ldw, st, lp + 1));
+            refresh_bw(lp + 1);
+            if (pass == 0) normalize(opt.drop_tol, lp + 1);
+        }
+    }
+
+    // Algorithm 3 on columns [s, e)
+    void rec(int s, int e, int c) {
+        const int len = e - s;
+        if (len <= 0) return;
+        if (len <= c) {
+            const int L = new_loop();
+            for (int pass = 0; pass < opt.max_pass; ++pass) {
+                int *lp = loop(L);
+                gram_self(s, len, Ml, lp);
+                chk(orth_leaf(Ml, len, opt.drop_tol, opt.orth_tol, opt.skip_final ? 1 : 0, ints, s, Sl, lp, st));
+                update(s, len, Sl, len, s, len, 1.0, 0.0, lp + 1);
+            }
+            return;
+        }
+        const int s2 = s + len / 2, l2 = e - s2;
+        rec(s, s2, c);
+        const int L = new_loop();
+        for (int pass = 0; pass < opt.max_pass; ++pass) {
+            int *lp = loop(L);
+            gram_w(s, s2 - s, s2, l2, Rn, lp);
+            chk(orth_pass_test(Rn, s2 - s, l2, l2, opt.orth_tol, opt.skip_final ? 1 : 0, 1, lp, st));
+            update(s, s2 - s, Rn, l2, s2, l2, -1.0, 1.0, lp + 1);
+        }
+        rec(s2, e, c);
+    }
+
+    // Algorithm 2 on columns [0, k): blocks of b columns; inside a block each
+    // column is B-orthogonalized against the block's earlier columns by
+    // Gram-Schmidt (two passes, one reduction each: the coefficients and the
+    // column's own squared B-norm, the norm after the projection following by
+    // Pythagoras), normalized or dropped (squared B-norm after the projection
+    // at most drop_tol; the columns enter with unit B-norm), then the block is
+    // deflated from all later columns (repeated until the coefficients are small)
+    void mbo(int b) {
+        double *cvec = Rn + (size_t)k * k;   // (nu + 1) coefficients of one column
+        for (int cur = 0; cur < k; cur += b) {
             const int blk_end = std::min(cur + b, k);
-            const int bs0 = out;
             for (int j = cur; j < blk_end; ++j) {
-                // one reduction per pass: [U, w]^T B w gives the coefficients
-                // against the block's kept columns U and the squared B-norm of w
-                double nrm0 = 0.0, nrm = 0.0;
+                const int nu = j - cur;
                 for (int pass = 0; pass < 2; ++pass) {
-                    const int nu = out - bs0;
                     Segs X;
-                    std::vector<double> c;
-                    int rc;
                     if (csr()) {
-                        X.add(BW + bs0, ldbw, nu);
+                        X.add(BW + cur, ldbw, nu);
                         X.add(BW + j, ldbw, 1);
                     } else {
-                        X.add(W + bs0, ldw, nu);
+                        X.add(W + cur, ldw, nu);
                         X.add(W + j, ldw, 1);
                     }
-                    rc = gram_host(X, W + j, ldw, 1, csr(), c);
-                    if (rc) return rc;
-                    double cc = 0.0;
-                    for (int i = 0; i < nu; ++i) cc += c[i] * c[i];
-                    if (pass == 0) nrm0 = c[nu];
-                    nrm = c[nu] - cc;   // squared B-norm after this pass's projection
-                    if (nu == 0) break;
-                    c.resize(nu);
-                    Segs Uw;
-                    Uw.add(W + bs0, ldw, nu);
-                    rc = gemm_host(Uw, c, 1, -1.0, 1.0, W + j, ldw);
-                    if (rc) return rc;
-                    if (csr()) {
-                        Segs Ub;
-                        Ub.add(BW + bs0, ldbw, nu);
-                        rc = gemm_host(Ub, c, 1, -1.0, 1.0, BW + j, ldbw);
-                        if (rc) return rc;
-                    }
+                    chk(gram(n, X, W + j, ldw, 1, csr() ? nullptr : dweight(), cvec, 1, ws, st));
+                    ++grams;
+                    chk(orth_mbo_coef(cvec, nu, pass, state, st));
+                    update(cur, nu, cvec, 1, j, 1, -1.0, 1.0, nullptr);
                 }
-                // columns enter with unit B-norm (normalized after the deflation
-                // against Q), so the squared norm left is compared with drop_tol
-                // itself: a column that the deflations of earlier blocks reduced
-                // to rounding is dependent too
-                const bool keep = nrm0 > 0.0 && std::isfinite(nrm) && nrm > opt.drop_tol;
-                if (!keep) {
-                    if (os) os->dropped++;
-                    continue;
-                }
-                const double sc = 1.0 / std::sqrt(nrm);
-                e = stg.upload(ws.colvec, &sc, sizeof(double));
-                if (e == hipSuccess) e = copy_cols<double, double>(n, 1, W + j, ldw, W + out, ldw, ws.colvec, st);
-                if (e == hipSuccess && csr()) e = copy_cols<double, double>(n, 1, BW + j, ldbw, BW + out, ldbw, ws.colvec, st);
-                if (e != hipSuccess) return fail(e, "normalize");
-                ++out;
+                chk(orth_mbo_keep(state, opt.drop_tol, ints, j, scale + j, st));
+                chk(copy_cols<double, double>(n, 1, W + j, ldw, W + j, ldw, scale + j, st));
+                if (csr()) chk(copy_cols<double, double>(n, 1, BW + j, ldbw, BW + j, ldbw, scale + j, st));
             }
-            const int nb = out - bs0, nr = k - blk_end;
-            if (nb > 0 && nr > 0) {
-                for (int pass = 0; pass < opt.max_pass; ++pass) {
-                    Segs X1;
-                    std::vector<double> R;
-                    int rc;
-                    if (csr()) {
-                        X1.add(BW + bs0, ldbw, nb);
-                        rc = gram_host(X1, W + blk_end, ldw, nr, true, R);
-                    } else {
-                        X1.add(W + bs0, ldw, nb);
-                        rc = gram_host(X1, W + blk_end, ldw, nr, false, R);
-                    }
-                    if (rc) return rc;
-                    double rmax = 0.0;
-                    for (double v : R) rmax = std::max(rmax, std::fabs(v));
-                    Segs W1;
-                    W1.add(W + bs0, ldw, nb);
-                    rc = gemm_host(W1, R, nr, -1.0, 1.0, W + blk_end, ldw);
-                    if (rc) return rc;
-                    if (csr()) {
-                        Segs B1;
-                        B1.add(BW + bs0, ldbw, nb);
-                        rc = gemm_host(B1, R, nr, -1.0, 1.0, BW + blk_end, ldbw);
-                        if (rc) return rc;
-                    }
-                    if (rmax <= opt.orth_tol) break;
-                }
-            }
-            cur = blk_end;
-        }
-        *kept = out;
-        return GCGE_OK;
-    }
-
-    // Algorithm 3 on columns [s, e); returns kept count via *kept
-    int rec(int s, int e, int *kept) {
-        const int len = e - s;
-        if (len <= 0) {
-            *kept = 0;
-            return GCGE_OK;
-        }
-        if (len <= c) {
-            int k = len;
-            for (int pass = 0; pass < opt.max_pass && k > 0; ++pass) {
-                Segs X;
-                X.add(W + s, ldw, k);
-                std::vector<double> M;
-                int rc = csr() ? gram_host(X, BW + s, ldbw, k, true, M) : gram_host(X, W + s, ldw, k, false, M);
-                if (rc) return rc;
-                for (int i = 0; i < k; ++i)
-                    for (int j = i + 1; j < k; ++j) M[i * k + j] = M[j * k + i] = 0.5 * (M[i * k + j] + M[j * k + i]);
-                std::vector<double> lam(k), Q((size_t)k * k);
-                if (jacobi_small(k, M.data(), lam.data(), Q.data()) != 0) {
-                    err = "leaf eigensolve did not converge";
-                    return GCGE_ERR_INTERNAL;
-                }
-                int kk = 0;
-                double dev = 0.0;
-                std::vector<int> keepc;
-                for (int j = 0; j < k; ++j)
-                    if (lam[j] > opt.drop_tol && std::isfinite(lam[j])) keepc.push_back(j);
-                kk = (int)keepc.size();
-                std::vector<double> S((size_t)k * std::max(kk, 1));
-                for (int q = 0; q < kk; ++q) {
-                    const int j = keepc[q];
-                    dev = std::max(dev, std::fabs(lam[j] - 1.0));
-                    const double isq = 1.0 / std::sqrt(lam[j]);
-                    for (int i = 0; i < k; ++i) S[(size_t)i * kk + q] = Q[(size_t)i * k + j] * isq;
-                }
-                if (opt.skip_final && kk == k && dev <= opt.orth_tol) break;   // already orthonormal
-                if (os) os->dropped += k - kk;
-                if (kk > 0) {
-                    rc = gemm_host(X, S, kk, 1.0, 0.0, W + s, ldw);
-                    if (rc) return rc;
-                    if (csr()) {
-                        Segs XB;
-                        XB.add(BW + s, ldbw, k);
-                        rc = gemm_host(XB, S, kk, 1.0, 0.0, BW + s, ldbw);
-                        if (rc) return rc;
-                    }
-                }
-                k = kk;
-                if (dev <= opt.orth_tol) break;
-            }
-            *kept = k;
-            return GCGE_OK;
-        }
-        const int h = len / 2;
-        int k1 = 0, k2 = 0;
-        int rc = rec(s, s + h, &k1);
-        if (rc) return rc;
-        const int s2 = s + h, l2 = e - s2;
-        if (k1 > 0) {
+            const int nb = blk_end - cur, nr = k - blk_end;
+            if (nr <= 0) continue;
+            const int L = new_loop();
             for (int pass = 0; pass < opt.max_pass; ++pass) {
-                Segs X1;
-                std::vector<double> R;
-                if (csr()) {
-                    X1.add(BW + s, ldbw, k1);
-                    rc = gram_host(X1, W + s2, ldw, l2, true, R);
-                } else {
-                    X1.add(W + s, ldw, k1);
-                    rc = gram_host(X1, W + s2, ldw, l2, false, R);
-                }
-                if (rc) return rc;
-                double rmax = 0.0;
-                for (double v : R) rmax = std::max(rmax, std::fabs(v));
-                if (opt.skip_final && rmax <= opt.orth_tol) break;
-                Segs W1;
-                W1.add(W + s, ldw, k1);
-                rc = gemm_host(W1, R, l2, -1.0, 1.0, W + s2, ldw);
-                if (rc) return rc;
-                if (csr()) {
-                    Segs B1;
-                    B1.add(BW + s, ldbw, k1);
-                    rc = gemm_host(B1, R, l2, -1.0, 1.0, BW + s2, ldbw);
-                    if (rc) return rc;
-                }
-                if (rmax <= opt.orth_tol) break;
+                int *lp = loop(L);
+                gram_w(cur, nb, blk_end, nr, Rn, lp);
+                chk(orth_pass_test(Rn, nb, nr, nr, opt.orth_tol, 0, 1, lp, st));
+                update(cur, nb, Rn, nr, blk_end, nr, -1.0, 1.0, lp + 1);
             }
         }
-        rc = rec(s2, e, &k2);
-        if (rc) return rc;
-        if (k1 < h && k2 > 0) {
-            hipError_t ee = shift_cols_left(n, W, ldw, s + k1, s2, k2, st);
-            if (ee == hipSuccess && csr()) ee = shift_cols_left(n, BW, ldbw, s + k1, s2, k2, st);
-            if (ee != hipSuccess) return fail(ee, "compact");
-        }
-        *kept = k1 + k2;
-        return GCGE_OK;
     }
 };
 
@@ -649,46 +533,58 @@ int orth_block(int64_t n, const BOp &B, const Segs &Q, double *W, int64_t ldw, i
                std::string &err) {
     *kept = 0;
     if (k <= 0) return GCGE_OK;
-    OrthCtx C{n, B, W, ldw, BW, ldbw, opt, ws, stg, st, os, err, 16};
-    int rc = C.refresh_bw(0, k);
-    if (rc) return rc;
+    DevOrth D{n, B, W, ldw, BW, ldbw, k, opt, ws, st, err};
+    const int mq = Q.total();
+    const int b2 = opt.mbo_block > 0 ? std::min(opt.mbo_block, k) : std::max(1, std::min(k / 4, 200));
+    D.nloops = 1 + (opt.algorithm == 2 ? (k + b2 - 1) / b2 : 2 * k);
+    // device state: coefficient blocks, then the flags
+    const size_t big = (size_t)std::max(mq, k) * k;
+    const size_t kr = ((size_t)k + 31) / 32 * 32;
+    const size_t ndbl = big + 256 + 256 + (size_t)k * k + kr + kr + 8;
+    const size_t nint = ORTH_ALIVE + k + 2 * (size_t)D.nloops;
+    // the Gram partials are sized for the largest product once, so that no
+    // buffer is reallocated while the sequence below is in flight
+    hipError_t e = ws.ensure_orth(ndbl * sizeof(double) + nint * sizeof(int) + 256);
+    if (e == hipSuccess) e = ws.ensure_part(gram_part_bytes_max());
+    if (e != hipSuccess) {
+        err = std::string("workspace: ") + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP;
+    }
+    double *base = reinterpret_cast<double *>(ws.orth);
+    D.G = base;
+    D.Ml = D.G + big;
+    D.Sl = D.Ml + 256;
+    D.Rn = D.Sl + 256;                       // k x k, then k Algorithm 2 column coefficients
+    D.scale = D.Rn + (size_t)k * k + kr;
+    D.state = D.scale + kr;
+    D.ints = reinterpret_cast<int *>(D.state + 8);
+
+    D.chk(orth_init(D.ints, k, D.nloops, st));
+    D.refresh_bw(nullptr);
+    D.normalize(0.0, nullptr);   // exact zero columns only
+    if (mq > 0) D.deflate(Q);
+    if (opt.algorithm == 2) D.mbo(b2);
+    else D.rec(0, k, std::min(k, 16));
+    D.chk(orth_finish(n, W, ldw, k, D.ints, st));
+    if (D.e != hipSuccess) {
+        err = std::string("orthogonalization: ") + hipGetErrorString(D.e);
+        return D.e == hipErrorOutOfMemory ? GCGE_ERR_OOM : GCGE_ERR_HIP;
+    }
     int kk = 0;
-    rc = C.normalize(0, k, 0.0, &kk);   // exact zero columns only
-    if (rc) return rc;
-    if (Q.total() > 0 && kk > 0) {
-        for (int pass = 0; pass < opt.max_pass && kk > 0; ++pass) {
-            std::vector<double> R;
-            rc = C.csr() ? C.gram_host(Q, BW, ldbw, kk, true, R) : C.gram_host(Q, W, ldw, kk, false, R);
-            if (rc) return rc;
-            double rmax = 0.0;
-            for (double v : R) rmax = std::max(rmax, std::fabs(v));
-            if (opt.skip_final && pass > 0 && rmax <= opt.orth_tol) break;
-            rc = C.gemm_host(Q, R, kk, -1.0, 1.0, W, ldw);
-            if (rc) return rc;
-            rc = C.refresh_bw(0, kk);
-            if (rc) return rc;
-            if (pass == 0) {
-                // columns that were (almost) inside span(Q) are dependent: drop them
-                int k2 = 0;
-                rc = C.normalize(0, kk, opt.drop_tol, &k2);
-                if (rc) return rc;
-                kk = k2;
-            } else if (rmax <= opt.orth_tol) {
-                break;
-            }
-        }
+    e = stg.download(&kk, D.ints, sizeof(int));
+    if (e != hipSuccess) {
+        err = std::string("orthogonalization: ") + hipGetErrorString(e);
+        return GCGE_ERR_HIP;
     }
-    if (kk == 0) return GCGE_OK;
-    int out = 0;
-    if (opt.algorithm == 2) {
-        const int b = opt.mbo_block > 0 ? opt.mbo_block : std::max(1, std::min(kk / 4, 200));
-        rc = C.mbo(kk, b, &out);
-    } else {
-        C.c = std::min(kk, 16);
-        rc = C.rec(0, kk, &out);
+    if (kk < 0 || kk > k) {
+        err = "orthogonalization: inconsistent kept count";
+        return GCGE_ERR_INTERNAL;
     }
-    if (rc) return rc;
-    *kept = out;
+    *kept = kk;
+    if (os) {
+        os->grams += D.grams;
+        os->dropped += k - kk;
+    }
     return GCGE_OK;
 }
 

