@@ -268,6 +268,7 @@ struct gcge_handle_s {
     double *Pb[2] = {nullptr, nullptr};
     double *Wb = nullptr, *AWb = nullptr, *BWb = nullptr, *Rb = nullptr;
     int64_t ldB = 0;
+    int64_t ldR = 0;   // R holds 2 ldB columns: after locking c pairs the CG reads R + c
     double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};
     float *cg32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void *cgmem = nullptr;
@@ -310,7 +311,7 @@ struct gcge_handle_s {
     int ensure_buffers(int bs, int capx, int prec);
     int do_residual(const double *X, int64_t ldx, int k, const double *lam_host, const double *lam_dev, double *R,
                     int64_t ldr, std::vector<double> &rn, std::vector<double> &bn, std::vector<double> *lam_out);
-    int do_cg(double theta, int k, const std::vector<double> &rn, int64_t *cg_its);
+    int do_cg(double theta, const double *R, int64_t ldr, int k, const std::vector<double> &rn, int64_t *cg_its);
     int gram_host(const Segs &X, const double *Y, int64_t ldy, int k, const double *d, std::vector<double> &C);
     int ritz_rotate(const Segs &V, int dim, int nwant, double *Y, int64_t ldy);
     int step5(const Segs &Vold, int dim_old, int nxh_old, int shift, int act_old, int bsa2, double *P, int *launched);
@@ -390,6 +391,7 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
     ldX = round_up(capx, 4);
     ldC = round_up(nev, 4);
     ldB = round_up(bs, 4);
+    ldR = 2 * ldB;
     hipError_t e = hipSuccess;
     auto A = [&](void **p, size_t bytes) {
         if (e == hipSuccess) e = bufs.alloc(p, bytes);
@@ -401,7 +403,7 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
     A((void **)&Pb[1], sizeof(double) * n * ldB);
     A((void **)&Wb, sizeof(double) * n * ldB);
     A((void **)&AWb, sizeof(double) * n * ldB);
-    A((void **)&Rb, sizeof(double) * n * ldB);
+    A((void **)&Rb, sizeof(double) * n * ldR);
     if (op.bkind == GCGE_B_CSR) A((void **)&BWb, sizeof(double) * n * ldB);
     A((void **)&mval, sizeof(double) * std::max<int64_t>(op.nnz, 1));
     if (prec % 2 == GCGE_PREC_FP64) {
@@ -491,7 +493,8 @@ int gcge_handle_s::do_residual(const double *X, int64_t ldx, int k, const double
     return GCGE_OK;
 }
 
-int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int64_t *cg_its) {
+int gcge_handle_s::do_cg(double theta, const double *R, int64_t ldr, int k, const std::vector<double> &rn,
+                         int64_t *cg_its) {
     const bool mixed = (precision == GCGE_PREC_MIXED);
     hipError_t e = hipSuccess;
     if (!m_valid || theta != theta_cur || (mixed && !m32_valid)) {
@@ -517,10 +520,10 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
                 amg_setup_ms = ms_since(ta);
             }
             cs.rz = (double *)(cm + 7 * slot);
-            return runner.run_pcg(M, amg, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1],
+            return runner.run_pcg(M, amg, R, ldr, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1],
                                   cg64[2], cg64[3], ldB, cs, cg_its);
         }
-        return runner.run(M, Rb, ldB, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
+        return runner.run(M, R, ldr, nullptr, k, cg_max_iter, cg_rel_tol, Wb, cg64[0], cg64[1], cg64[2], ldB, cs,
                           cg_its);
     }
     // FP32: right-hand side scaled to unit column norms, delta scaled back on output
@@ -552,10 +555,10 @@ int gcge_handle_s::do_cg(double theta, int k, const std::vector<double> &rn, int
         }
         amg.set_level0_f32(M);
         cs.rz = (float *)(cm + 7 * slot);
-        rc = runner.run_pcg(M, amg, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3],
+        rc = runner.run_pcg(M, amg, R, ldr, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3],
                             cg32[4], ldB, cs, cg_its);
     } else {
-        rc = runner.run(M, Rb, ldB, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
+        rc = runner.run(M, R, ldr, dsc, k, cg_max_iter, cg_rel_tol, cg32[0], cg32[1], cg32[2], cg32[3], ldB, cs,
                         cg_its);
     }
     if (rc) return rc;
@@ -660,7 +663,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         int bsa = std::min({bs, nev - ell, nx});
         if (bsa <= 0) return fail(GCGE_ERR_INTERNAL, "empty active block");
         double *Xu = Xb[cur] + off;
-        rc = do_residual(Xu, ldX, bsa, nullptr, rr_w + woff, Rb, ldB, rn, bn, &lamv);
+        rc = do_residual(Xu, ldX, bsa, nullptr, rr_w + woff, Rb, ldR, rn, bn, &lamv);
         if (rc) return rc;
         S.spmm_columns += bsa;
         int c = 0;
@@ -690,12 +693,25 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         if (rc) return rc;
         S.time_ms[4] += ms_since(t5);
 
-        // residuals of the shifted active block
+        // residuals of the shifted active block: the first bsa - c are those of
+        // STEP 4 (columns c .. bsa-1 of R, which the CG reads from R + c); only
+        // the columns entering the block are computed, into R + bsa
+        const double *Rcur = Rb + c;
         if (c > 0) {
             auto t4b = Clock::now();
-            rc = do_residual(Xu, ldX, bsa2, nullptr, rr_w + woff, Rb, ldB, rn, bn, nullptr);
-            if (rc) return rc;
-            S.spmm_columns += bsa2;
+            rn.erase(rn.begin(), rn.begin() + c);
+            bn.erase(bn.begin(), bn.begin() + c);
+            const int have = bsa - c, nnew = bsa2 - have;
+            if (nnew > 0) {
+                std::vector<double> rn2, bn2;
+                rc = do_residual(Xu + have, ldX, nnew, nullptr, rr_w + woff + have, Rb + bsa, ldR, rn2, bn2, nullptr);
+                if (rc) return rc;
+                rn.insert(rn.end(), rn2.begin(), rn2.end());
+                bn.insert(bn.end(), bn2.begin(), bn2.end());
+                S.spmm_columns += nnew;
+            }
+            rn.resize(bsa2);
+            bn.resize(bsa2);
             S.time_ms[3] += ms_since(t4b);
         }
 
@@ -704,7 +720,7 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
         double theta = 0.0;
         if (shift && !precond && ell > 0) theta = *std::max_element(lam_lock.begin(), lam_lock.begin() + ell);
         int64_t cgi = 0;
-        rc = do_cg(theta, bsa2, rn, &cgi);
+        rc = do_cg(theta, Rcur, ldR, bsa2, rn, &cgi);
         if (rc) return rc;
         S.cg_iterations += cgi;
         S.spmm_columns += cgi * bsa2;
