@@ -53,13 +53,16 @@ def flat_kernel(base, s, tail=""):
     return f"{base}<{'double' if s == 8 else 'float'}, {16 // s}{tail}>"
 
 
-def class_roofline(name, p, n, nnz, s=8, bs=None):
+def class_roofline(name, p, n, nnz, s=8, bs=None, lazy=False):
     """Achieved rate of one kernel class from its HIP-event timings.
 
     Algorithmic bytes per launch with k columns (s bytes per scalar):
       CG SpMM        nnz (4 + s) + 4 (n + 1) + 2 n k s   (CSR once, p gathered once, q written once)
       CG r update    3 n k s                              (q, r read; r written)
       CG x, p update 5 n k s                              (x, p, r read; x, p written)
+        with the search-direction history (lazy): p update 3 n k s (p, r read; new p written)
+      CG iterate     n s c                                (c = the launch's column count: the
+                     from the history                     terms and x, times k)
     For the CG classes only the launches over a full block (k = bs columns, one
     kernel instance) are used.  Flops per launch of the GEMMs and Grams with
     m x k coefficient blocks: 2 n m k."""
@@ -76,8 +79,12 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
     hbm = {"cg_spmm": lambda: (nnz * (4 + s) + 4 * (n + 1) + 2 * n * k * s,
                                row_kernel("k_spmms", s, kr, ", 0, 2") + " (CG: q = (A - theta B) p with p.q)"),
            "cg_update_r": lambda: (3 * n * k * s, flat_kernel("k_cg_update_r_pk", s, ", 4") + " (CG: r -= alpha q, r.r)"),
-           "cg_update_xp": lambda: (5 * n * k * s,
-                                    flat_kernel("k_cg_update_xp_flat", s) + " (CG: x += alpha p, p = r + beta p)")}
+           "cg_update_xp": lambda: ((3 * n * k * s, flat_kernel("k_cg_update_p_flat", s)
+                                     + " (CG: p_new = r + beta p, search-direction history)") if lazy else
+                                    (5 * n * k * s, flat_kernel("k_cg_update_xp_flat", s)
+                                     + " (CG: x += alpha p, p = r + beta p)")),
+           "cg_fold": lambda: (n * s * p["columns"] / p["launches"],
+                               flat_kernel("k_cg_fold", s) + " (CG: x = sum_i alpha_i p_i from the history)")}
     if name in hbm:
         per_launch, kern = hbm[name]()
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
@@ -98,24 +105,32 @@ def class_roofline(name, p, n, nnz, s=8, bs=None):
             "algorithmic_flops_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": p["launches"]}
 
 
-def cg_iteration_roofline(kr):
+def cg_iteration_roofline(kr, lazy=False):
     """One full-block CG iteration (its three kernels) as one HBM-bound step:
     the sum of their algorithmic bytes over the sum of their average
-    full-block launch times."""
+    full-block launch times.  With the search-direction history the third
+    kernel is the p update alone; the iterate, formed once per CG solve, is
+    the class cg_fold."""
     parts = [kr.get(c) for c in ("cg_spmm", "cg_update_r", "cg_update_xp")]
     if any(p is None for p in parts):
         return None
     b = sum(p["algorithmic_bytes_per_launch"] for p in parts)
     ms = sum(p["avg_launch_ms"] for p in parts)
     achieved = b / (ms * 1e-3) / 1e9
-    return {"kernels": "SpMM + r update + x/p update", "bound": "hbm", "algorithmic_bytes": b, "ms": ms,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+    return {"kernels": "SpMM + r update + " + ("p update" if lazy else "x/p update"), "bound": "hbm",
+            "algorithmic_bytes": b, "ms": ms, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS}
 
 
-def dominant_roofline(prof, n, nnz, s=8, bs=None):
+def dominant_roofline(prof, n, nnz, s=8, bs=None, lazy=False):
     """Roofline entry of the kernel class with the largest summed device time."""
     name = max(prof, key=lambda c: prof[c]["ms"])
-    return class_roofline(name, prof[name], n, nnz, s, bs), name
+    return class_roofline(name, prof[name], n, nnz, s, bs, lazy), name
+
+
+def uses_history(prof):
+    """True when the CG formed its iterates from the search-direction history."""
+    return prof.get("cg_fold", {}).get("launches", 0) > 0
 
 
 def sum_prof(stats):
@@ -363,6 +378,8 @@ def main():
     ap.add_argument("--orth-skip-final", type=int, choices=(0, 1), default=0,
                     help="1: Algorithm 3's pass loops stop before the update of a pass that already "
                          "meets the tolerance (the paper's listing applies it)")
+    ap.add_argument("--cg-history", type=int, default=32,
+                    help="inner CG search-direction history slots (0: update the iterate in every step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=32,
                     help="grid of the reduced input that the CPU oracle and the GPU both solve for cpu_baseline")
@@ -419,7 +436,7 @@ def main():
         launch of the main kernel classes bracketed by HIP events."""
         opts = dict(block_size=bs, precision=prec, moving=int(p["moving"]), profile=0, orth=args.orth,
                     cg_max_iter=args.cg_max_iter, cg_rel_tol=args.cg_rel_tol, shift=args.shift,
-                    precond=args.precond, orth_skip_final=args.orth_skip_final)
+                    precond=args.precond, orth_skip_final=args.orth_skip_final, cg_history=args.cg_history)
         with g.Solver(Ad, Bd, nev, tol, **opts) as s:
             for i in range(warmup):
                 lam, _, st = s.solve(evecs)
@@ -456,6 +473,7 @@ def main():
                    "orthogonalization": ("Algorithm 3" if args.orth == 3 else "Algorithm 2")
                    + (", final sub-tolerance update skipped" if args.orth_skip_final else ""),
                    "cg_max_iter": args.cg_max_iter, "cg_rel_tol": args.cg_rel_tol, "shift": bool(args.shift),
+                   "cg_history": args.cg_history,
                    "inner_preconditioner": "algebraic multigrid V-cycle (theta = 0)" if args.precond else None},
     }
     st = s64[-1]
@@ -466,14 +484,17 @@ def main():
     out["solve"]["instrumented_solve_s"] = round(tp64, 4)
     # rooflines from every launch of the instrumented solve
     prof = sum_prof([sp64])
-    roof, name = dominant_roofline(prof, A.n, A.nnz, bs=bs)
+    lazy = uses_history(prof)
+    roof, name = dominant_roofline(prof, A.n, A.nnz, bs=bs, lazy=lazy)
     if roof is not None and roof.get("bound") == "hbm":
         roof["traffic"] = measured_traffic(roof["kernel"])
     out["roofline"] = add_measured_peak(roof, copy_gbs)
-    out["kernel_rooflines"] = {c: add_measured_peak(class_roofline(c, prof[c], A.n, A.nnz, bs=bs), copy_gbs)
+    out["kernel_rooflines"] = {c: add_measured_peak(class_roofline(c, prof[c], A.n, A.nnz, bs=bs, lazy=lazy),
+                                                    copy_gbs)
                                for c in prof}
     out["kernel_ms_per_solve"] = {c: round(prof[c]["ms"], 2) for c in prof}
-    out["cg_iteration_roofline"] = add_measured_peak(cg_iteration_roofline(out["kernel_rooflines"]), copy_gbs)
+    out["cg_iteration_roofline"] = add_measured_peak(cg_iteration_roofline(out["kernel_rooflines"], lazy), copy_gbs)
+    out["cg_search_direction_history"] = lazy
     out["copy_peak_gbs"] = copy_gbs
     if not args.no_mixed:
         tm, sm, lamm, spm, tpm = run("mixed", args.steps, args.warmup)
@@ -483,11 +504,12 @@ def main():
                         "iterations": sm[-1]["iterations"], "cg_iterations": sm[-1]["cg_iterations"],
                         "max_rel_residual": sm[-1]["max_rel_residual"], "dtype": "f32 inner CG, f64 elsewhere"}
         profm = sum_prof([spm])
-        out["mixed"]["kernel_rooflines"] = {c: add_measured_peak(class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs),
-                                                                 copy_gbs)
-                                            for c in ("cg_spmm", "cg_update_r", "cg_update_xp")}
+        lazym = uses_history(profm)
+        out["mixed"]["kernel_rooflines"] = {
+            c: add_measured_peak(class_roofline(c, profm[c], A.n, A.nnz, s=4, bs=bs, lazy=lazym), copy_gbs)
+            for c in ("cg_spmm", "cg_update_r", "cg_update_xp", "cg_fold")}
         out["mixed"]["cg_iteration_roofline"] = add_measured_peak(
-            cg_iteration_roofline(out["mixed"]["kernel_rooflines"]), copy_gbs)
+            cg_iteration_roofline(out["mixed"]["kernel_rooflines"], lazym), copy_gbs)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on the {args.cpu_grid}^3 grid, {host_threads()} threads")
         out["cpu_baseline"] = cpu_baseline(g, args.workload, args.cpu_grid, dev)

@@ -90,9 +90,13 @@ typedef struct {
      * the summed column count of the launches (for the GEMMs and Grams: the
      * product of the two column counts).  Classes: 0 CG SpMM (q = (A - theta
      * B) p with p.q), 1 CG residual update (r -= alpha q with r.r), 2 CG
-     * iterate and direction update (x += alpha p, p = r + beta p), 3 Ritz
-     * rotation (V_u xhat), 4 P block (V_u phat), 5 Gram products of the
-     * solver driver (initial and Rayleigh-Ritz); 6 and 7 are unused (zero). */
+     * iterate and direction update (x += alpha p, p = r + beta p; with a
+     * search-direction history only p_new = r + beta p), 3 Ritz rotation (V_u
+     * xhat), 4 P block (V_u phat), 5 Gram products of the solver driver
+     * (initial and Rayleigh-Ritz), 6 the multigrid V-cycle of the
+     * preconditioned CG, 7 the CG iterate formed from the history (x = sum_i
+     * alpha_i p_i; columns = block width times the n-vectors it moves: the
+     * terms read, x written, and x read when it already held earlier terms). */
     double prof_ms[8];
     int64_t prof_launches[8];
     int64_t prof_columns[8];
@@ -122,6 +126,14 @@ int gcge_create(const gcge_csr *A, int b_kind, const void *B, int nev, double to
  *  "size_x"       [min(nev + 3*block_size, n)]  sizeX (Section 3.2, remark on sizeX)
  *  "max_iter"     [1000]  GCG iterations before GCGE_NOT_CONVERGED
  *  "cg_max_iter"  [30]    inner CG iterations (Section 4.1)
+ *  "cg_history"   [32]    0, or 2 .. 32: the inner CG keeps up to min(cg_history,
+ *                         cg_max_iter + 1) search directions in device memory (n x
+ *                         block_size each, in the CG precision; at most half of the free
+ *                         device memory, else fewer slots, else none) and forms the
+ *                         correction as sum_i alpha_i p_i when they are used up and at
+ *                         the end, in place of an update of it in every CG step: the
+ *                         same result to the bit with two fewer passes over an n x
+ *                         block_size block per step.  0 updates it in every step.
  *  "precision"    [GCGE_PREC_FP64]
  *  "moving"       [0]     moving mechanism, maxProjDim = 5*block_size (Section 3.3)
  *  "shift"        [1]     dynamic shift theta = largest converged eigenvalue (Section 3.2, STEP 6);

@@ -96,7 +96,7 @@ def _b_args(B):
 
 _INT_OPTS = {"block_size", "size_x", "max_iter", "cg_max_iter", "precision", "moving", "shift", "seed", "check",
              "dense_eig", "orth", "orth_block", "orth_skip_final", "precond", "amg_levels", "amg_coarse",
-             "profile"}
+             "profile", "cg_history"}
 _DBL_OPTS = {"tol", "cg_rel_tol", "orth_tol", "drop_tol", "amg_strength"}
 
 

@@ -18,7 +18,7 @@ GCGE_ERR_INTERNAL = -5
 B_IDENTITY, B_DIAG, B_CSR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
-PROF_NAMES = ["cg_spmm", "cg_update_r", "cg_update_xp", "rotation_gemm", "p_gemm", "gram", "amg_vcycle", "unused7"]
+PROF_NAMES = ["cg_spmm", "cg_update_r", "cg_update_xp", "rotation_gemm", "p_gemm", "gram", "amg_vcycle", "cg_fold"]
 STEP_NAMES = ["init", "step2_orth", "step3_rr", "step4_conv", "step5_p", "step6_cg", "final_check", "total"]
 
 # Every symbol declared in include/gcge.h.

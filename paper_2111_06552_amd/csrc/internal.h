@@ -146,6 +146,21 @@ template <typename T>
 hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> cs, hipStream_t st);
 template <typename T>
 hipError_t cg_update_xp(int64_t n, int k, T *x, T *p, const T *r, int64_t ld, CgState<T> cs, hipStream_t st);
+// Search-direction history (k_cg_update_p_flat, k_cg_fold in kernels.hip):
+// cg_hist_ok tells whether a ring of H slots of n x ld vectors can be used
+// for k columns (2 <= H <= 32, the flat 16-byte layout); cg_update_p writes
+// pn = s + beta p; cg_fold adds sum_j alpha_j p_j over steps first ..
+// first+count-1 to x (x = that sum when init), slot j mod H of hist (stride
+// sstride elements), alpha_j row j mod H of ar (stride astride).
+constexpr int CG_HIST_MAX = 32;
+template <typename T>
+bool cg_hist_ok(int64_t n, int k, int64_t ld, int H);
+template <typename T>
+hipError_t cg_update_p(int64_t n, int k, const T *p, T *pn, const T *s, int64_t ld, CgState<T> cs,
+                       hipStream_t st);
+template <typename T>
+hipError_t cg_fold(int64_t n, int k, T *x, int64_t ld, const T *hist, int64_t sstride, int H, const T *ar,
+                   int astride, int first, int count, bool init, hipStream_t st);
 // Y = diag(d) X (n x k row-major).
 template <typename T>
 hipError_t scale_rows(int64_t n, int k, const T *d, const T *X, int64_t ldx, T *Y, int64_t ldy, hipStream_t st);

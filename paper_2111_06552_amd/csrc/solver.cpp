@@ -110,7 +110,12 @@ struct KProf {
     }
 };
 
-// Column-wise CG driver shared by the solver and gcge_cg.
+// Column-wise CG driver shared by the solver and gcge_cg.  With a
+// search-direction history (hist_slots >= 2 slots of n x ld vectors at hist,
+// alpha rows at hist_alpha) the directions go to the ring and x is formed by
+// cg_fold (before a slot still needed would be overwritten, and at the end)
+// instead of an update of x in every step; the results are the same to the
+// bit.
 template <typename T>
 struct CgRunner {
     int64_t n;
@@ -120,6 +125,29 @@ struct CgRunner {
     hipEvent_t ev;
     std::string &err;
     KProf *prof = nullptr;
+    T *hist = nullptr;
+    int hist_slots = 0;
+    T *hist_alpha = nullptr;
+
+    static constexpr int ASTRIDE = 128;   // alpha row stride of the history
+    bool lazy(int k, int64_t ld) const {
+        return hist != nullptr && hist_alpha != nullptr && cg_hist_ok<T>(n, k, ld, hist_slots);
+    }
+    T *slot(int j, int64_t ld) const { return hist + (size_t)(j % hist_slots) * n * ld; }
+    CgState<T> step_state(CgState<T> cs, int j) const {
+        cs.alpha = hist_alpha + (size_t)(j % hist_slots) * ASTRIDE;
+        return cs;
+    }
+    // x (+)= the terms of steps first .. end-1 (class 7 of the profile; its
+    // column count is the n-vectors moved: the terms, x written, x read
+    // unless init, times k)
+    hipError_t fold(T *x, int64_t ld, int k, int first, int end, bool init) {
+        const int pb = prof ? prof->begin(st) : -1;
+        const hipError_t e = cg_fold<T>(n, k, x, ld, hist, n * ld, hist_slots, hist_alpha, ASTRIDE, first,
+                                        end - first, init, st);
+        if (prof) prof->end(7, pb, (int64_t)k * (end - first + (init ? 1 : 2)), st);
+        return e;
+    }
 
     int run(const DevCsr<T> &M, const double *R, int64_t ldr, const double *rscale, int k, int maxit,
             double rel_tol, T *x, T *r, T *p, T *q, int64_t ld, CgState<T> cs, int64_t *total_its) {
@@ -127,23 +155,40 @@ struct CgRunner {
         if (e != hipSuccess) return fail(e, "workspace");
         T *part = (T *)ws.part;
         int nparts = 0;
-        e = cg_init<T>(R, ldr, rscale, k, n, r, p, x, ld, part, &nparts, cs, st);
+        const bool lz = lazy(k, ld);
+        int first = 0;        // first step not yet in x (history)
+        bool have_x = false;  // x holds the steps before first
+        e = cg_init<T>(R, ldr, rscale, k, n, r, lz ? slot(0, ld) : p, lz ? nullptr : x, ld, part, &nparts, cs, st);
         if (e == hipSuccess) e = cg_init_finish<T>(part, nparts, k, cs, st);
         if (e != hipSuccess) return fail(e, "cg init");
         bool pending = false;
         int it = 0;
         for (; it < maxit; ++it) {
+            const CgState<T> ci = lz ? step_state(cs, it) : cs;
+            T *pc = lz ? slot(it, ld) : p;
             int pb = prof ? prof->begin(st) : -1;
-            e = cg_spmm<T>(M, p, q, ld, k, part, &nparts, cs.flags, st);
+            e = cg_spmm<T>(M, pc, q, ld, k, part, &nparts, ci.flags, st);
             if (prof) prof->end(0, pb, k, st);
-            if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
+            if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, ci, st);
             pb = prof ? prof->begin(st) : -1;
-            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, cs, st);
+            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, ci, st);
             if (prof) prof->end(1, pb, k, st);
-            if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
-            pb = prof ? prof->begin(st) : -1;
-            if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, r, ld, cs, st);
-            if (prof) prof->end(2, pb, k, st);
+            if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, ci, st);
+            if (lz) {
+                // the slot of p_(it+1) still holds p_(it+1-H): fold through this step first
+                if (e == hipSuccess && it + 1 - first >= hist_slots) {
+                    e = fold(x, ld, k, first, it + 1, !have_x);
+                    first = it + 1;
+                    have_x = true;
+                }
+                pb = prof ? prof->begin(st) : -1;
+                if (e == hipSuccess) e = cg_update_p<T>(n, k, pc, slot(it + 1, ld), r, ld, ci, st);
+                if (prof) prof->end(2, pb, k, st);
+            } else {
+                pb = prof ? prof->begin(st) : -1;
+                if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, r, ld, cs, st);
+                if (prof) prof->end(2, pb, k, st);
+            }
             if (e != hipSuccess) return fail(e, "cg iteration");
             if (pinned_flag != nullptr && (it % 4) == 3) {
                 // non-blocking poll of the number of active columns
@@ -162,6 +207,10 @@ struct CgRunner {
                 }
             }
         }
+        if (lz && (it > first || !have_x)) {
+            e = fold(x, ld, k, first, it, !have_x);
+            if (e != hipSuccess) return fail(e, "cg iterate");
+        }
         if (total_its) *total_its += it;
         return GCGE_OK;
     }
@@ -173,34 +222,51 @@ struct CgRunner {
         if (e != hipSuccess) return fail(e, "workspace");
         T *part = (T *)ws.part;
         int nparts = 0;
-        e = cg_init<T>(R, ldr, rscale, k, n, r, p, x, ld, part, &nparts, cs, st);
+        const bool lz = lazy(k, ld);
+        int first = 0;
+        bool have_x = false;
+        T *p0 = lz ? slot(0, ld) : p;
+        e = cg_init<T>(R, ldr, rscale, k, n, r, p0, lz ? nullptr : x, ld, part, &nparts, cs, st);
         if (e == hipSuccess) e = cg_init_finish<T>(part, nparts, k, cs, st);
         if (e != hipSuccess) return fail(e, "pcg init");
         int rc = amg.apply<T>(r, ld, k, z, ld, part, &nparts, st, err);
         if (rc) return rc;
         e = pcg_rz<T>(part, nparts, k, true, cs, st);
-        if (e == hipSuccess) e = copy_cols<T, T>(n, k, z, ld, p, ld, nullptr, st);
+        if (e == hipSuccess) e = copy_cols<T, T>(n, k, z, ld, p0, ld, nullptr, st);
         if (e != hipSuccess) return fail(e, "pcg init");
         bool pending = false;
         int it = 0;
         for (; it < maxit; ++it) {
+            const CgState<T> ci = lz ? step_state(cs, it) : cs;
+            T *pc = lz ? slot(it, ld) : p;
             int pb = prof ? prof->begin(st) : -1;
-            e = cg_spmm<T>(M, p, q, ld, k, part, &nparts, cs.flags, st);
+            e = cg_spmm<T>(M, pc, q, ld, k, part, &nparts, ci.flags, st);
             if (prof) prof->end(0, pb, k, st);
-            if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, cs, st);
+            if (e == hipSuccess) e = cg_alpha<T>(part, nparts, k, ci, st);
             pb = prof ? prof->begin(st) : -1;
-            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, cs, st);
+            if (e == hipSuccess) e = cg_update_r<T>(n, k, q, r, ld, part, &nparts, ci, st);
             if (prof) prof->end(1, pb, k, st);
-            if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, cs, st);
+            if (e == hipSuccess) e = cg_beta<T>(part, nparts, k, rel_tol, ci, st);
             if (e != hipSuccess) return fail(e, "pcg iteration");
             pb = prof ? prof->begin(st) : -1;
-            rc = amg.apply<T>(r, ld, k, z, ld, part, &nparts, st, err, cs.flags);
+            rc = amg.apply<T>(r, ld, k, z, ld, part, &nparts, st, err, ci.flags);
             if (prof) prof->end(6, pb, k, st);
             if (rc) return rc;
-            e = pcg_rz<T>(part, nparts, k, false, cs, st);
-            pb = prof ? prof->begin(st) : -1;
-            if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, z, ld, cs, st);
-            if (prof) prof->end(2, pb, k, st);
+            e = pcg_rz<T>(part, nparts, k, false, ci, st);
+            if (lz) {
+                if (e == hipSuccess && it + 1 - first >= hist_slots) {
+                    e = fold(x, ld, k, first, it + 1, !have_x);
+                    first = it + 1;
+                    have_x = true;
+                }
+                pb = prof ? prof->begin(st) : -1;
+                if (e == hipSuccess) e = cg_update_p<T>(n, k, pc, slot(it + 1, ld), z, ld, ci, st);
+                if (prof) prof->end(2, pb, k, st);
+            } else {
+                pb = prof ? prof->begin(st) : -1;
+                if (e == hipSuccess) e = cg_update_xp<T>(n, k, x, p, z, ld, cs, st);
+                if (prof) prof->end(2, pb, k, st);
+            }
             if (e != hipSuccess) return fail(e, "pcg iteration");
             // A preconditioned iteration is long and few are needed: after
             // queuing an iteration, wait for the count of active columns copied
@@ -222,6 +288,10 @@ struct CgRunner {
                 if (e != hipSuccess) return fail(e, "pcg poll");
                 pending = true;
             }
+        }
+        if (lz && (it > first || !have_x)) {
+            e = fold(x, ld, k, first, it, !have_x);
+            if (e != hipSuccess) return fail(e, "pcg iterate");
         }
         if (total_its) *total_its += it;
         return GCGE_OK;
@@ -272,6 +342,12 @@ struct gcge_handle_s {
     double *cg64[4] = {nullptr, nullptr, nullptr, nullptr};
     float *cg32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void *cgmem = nullptr;
+    // inner CG search-direction history (option "cg_history": ring slots,
+    // 0 = update the iterate in every step): cghist_slots n x ldB vectors in
+    // the CG precision and their alpha rows
+    int cg_history = CG_HIST_MAX;
+    void *cghist = nullptr, *cghist_alpha = nullptr;
+    int cghist_slots = 0, cfg_hist = -1;
     double *mval = nullptr;
     float *mval32 = nullptr;
     double theta_cur = 0.0;
@@ -308,7 +384,7 @@ struct gcge_handle_s {
     }
     int hipfail(hipError_t e, const char *what) { return fail(hip_status(e), std::string(what) + ": " + hipGetErrorString(e)); }
 
-    int ensure_buffers(int bs, int capx, int prec);
+    int ensure_buffers(int bs, int capx, int prec, int hist);
     int do_residual(const double *X, int64_t ldx, int k, const double *lam_host, const double *lam_dev, double *R,
                     int64_t ldr, std::vector<double> &rn, std::vector<double> &bn, std::vector<double> *lam_out);
     int do_cg(double theta, const double *R, int64_t ldr, int k, const std::vector<double> &rn, int64_t *cg_its);
@@ -382,11 +458,13 @@ int gcge_handle_s::step5(const Segs &Vold, int dim_old, int nxh_old, int shift, 
     return GCGE_OK;
 }
 
-int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
-    if (bs == cfg_bs && capx == cfg_capx && prec == cfg_prec) return GCGE_OK;
+int gcge_handle_s::ensure_buffers(int bs, int capx, int prec, int hist) {
+    if (bs == cfg_bs && capx == cfg_capx && prec == cfg_prec && hist == cfg_hist) return GCGE_OK;
     bufs.release();
     m_valid = m32_valid = false;
-    cfg_bs = cfg_capx = cfg_prec = -1;
+    cfg_bs = cfg_capx = cfg_prec = cfg_hist = -1;
+    cghist = cghist_alpha = nullptr;
+    cghist_slots = 0;
     const int64_t n = op.n;
     ldX = round_up(capx, 4);
     ldC = round_up(nev, 4);
@@ -430,13 +508,30 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec) {
     A((void **)&rr_np, 64);
     rr_dmax = dmax;
     if (e == hipSuccess && dmax <= DENSE_EIG_MAX) e = eigw.ensure(dmax, dmax);
+    if (e == hipSuccess && hist >= 2) {
+        // the history takes at most half of the device memory still free
+        const size_t elem = (prec % 2 == GCGE_PREC_FP64) ? sizeof(double) : sizeof(float);
+        const size_t slot_bytes = elem * (size_t)n * ldB;
+        size_t fr = 0, tot = 0;
+        int H = 0;
+        if (slot_bytes > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess)
+            H = (int)std::min<size_t>((size_t)hist, fr / 2 / slot_bytes);
+        if (H >= 2) {
+            A(&cghist, slot_bytes * H);
+            A(&cghist_alpha, elem * 128 * H);
+            cghist_slots = H;
+        }
+    }
     if (e != hipSuccess) {
         bufs.release();
+        cghist = cghist_alpha = nullptr;
+        cghist_slots = 0;
         return hipfail(e, "buffer allocation");
     }
     cfg_bs = bs;
     cfg_capx = capx;
     cfg_prec = prec;
+    cfg_hist = hist;
     return GCGE_OK;
 }
 
@@ -510,6 +605,9 @@ int gcge_handle_s::do_cg(double theta, const double *R, int64_t ldr, int k, cons
         CgState<double> cs{(double *)cm, (double *)(cm + slot), (double *)(cm + 2 * slot), (double *)(cm + 3 * slot),
                            (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
         CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
+        runner.hist = (double *)cghist;
+        runner.hist_slots = cghist_slots;
+        runner.hist_alpha = (double *)cghist_alpha;
         DevCsr<double> M = op.csr_of(mval);
         if (precond) {
             if (!amg_valid) {
@@ -541,6 +639,9 @@ int gcge_handle_s::do_cg(double theta, const double *R, int64_t ldr, int k, cons
     CgState<float> cs{(float *)cm, (float *)(cm + slot), (float *)(cm + 2 * slot), (float *)(cm + 3 * slot),
                       (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
     CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
+    runner.hist = (float *)cghist;
+    runner.hist_slots = cghist_slots;
+    runner.hist_alpha = (float *)cghist_alpha;
     DevCsr<float> M = op.csr_of(mval32);
     int rc;
     if (precond) {
@@ -587,7 +688,8 @@ int gcge_handle_s::solve(double *evals, double *evecs, int64_t ldev, gcge_stats 
     const int sizeX = (int)sx;
     const int nx0 = mv ? (int)std::min<int64_t>(3 * (int64_t)bs, n) : sizeX;
     if (x0_k > nx0) return fail(GCGE_ERR_INVALID_ARG, "more initial vectors than the initial block holds");
-    int rc = ensure_buffers(bs, nx0, precision + 2 * precond);
+    const int hist = (cg_history >= 2 && cg_max_iter >= 1) ? std::min(cg_history, cg_max_iter + 1) : 0;
+    int rc = ensure_buffers(bs, nx0, precision + 2 * precond, hist);
     if (rc) return rc;
     stg.st = st;
     hipError_t e;
@@ -935,6 +1037,7 @@ extern "C" int gcge_set_option_i(gcge_handle h, const char *key, int64_t v) {
     else if (k == "seed") { h->seed = (uint64_t)v; }
     else if (k == "check") { if (v != 0 && v != 1) return bad(); h->check = (int)v; }
     else if (k == "profile") { if (v != 0 && v != 1) return bad(); h->profile = (int)v; }
+    else if (k == "cg_history") { if (v != 0 && (v < 2 || v > CG_HIST_MAX)) return bad(); h->cg_history = (int)v; }
     else if (k == "dense_eig") { if (v != 0 && v != 1) return bad(); h->dense_eig_opt = (int)v; }
     else if (k == "orth") { if (v != 2 && v != 3) return bad(); h->orth_alg = (int)v; }
     else if (k == "orth_block") { if (v < 0 || v > 100000) return bad(); h->orth_block_opt = (int)v; }

@@ -139,6 +139,42 @@ def test_deterministic(g):
     assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
 
 
+@pytest.mark.parametrize("prec,precond", [("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)])
+def test_cg_history_gives_the_same_solve_to_the_bit(g, prec, precond):
+    """The inner CG with a search-direction history forms x = sum_i alpha_i p_i
+    when the ring of H slots fills and at the end, in the order of the steps;
+    the solve is the same to the bit as with x updated in every step
+    (cg_history = 0), for every ring size, with and without the multigrid
+    preconditioner and in both precisions."""
+    A = wl.laplace3d_7pt(14)
+    d = wl.diag_uniform(A.n)
+    opts = dict(block_size=8, precision=prec, precond=precond)
+    ref = gpu_solve(g, A, "diag", d, 24, **opts, cg_history=0)
+    assert ref[2]["status"] == 0
+    for H in (2, 3, 7, 32):
+        r = gpu_solve(g, A, "diag", d, 24, **opts, cg_history=H)
+        # (cg_iterations counts the steps the host enqueued before its
+        # non-blocking poll saw convergence, a timing matter; the steps past
+        # convergence do nothing on the device)
+        assert r[2]["iterations"] == ref[2]["iterations"], H
+        assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1]), H
+    # a fixed CG length (no early stop) with a ring that fills several times
+    fixed = dict(block_size=8, precision=prec, precond=precond, cg_max_iter=9)
+    ref = gpu_solve(g, A, "diag", d, 24, **fixed, cg_history=0, cg_rel_tol=0.0)
+    r = gpu_solve(g, A, "diag", d, 24, **fixed, cg_history=4, cg_rel_tol=0.0)
+    assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1])
+
+
+def test_cg_history_option_range(g):
+    Ad = g.DeviceCsr.from_csr(wl.laplace3d_7pt(6))
+    with g.Solver(Ad, None, 4, 1e-8) as s:
+        for bad in (1, 33, -1):
+            with pytest.raises(Exception):
+                s.set_options(cg_history=bad)
+        s.set_options(cg_history=0)
+        s.set_options(cg_history=2)
+
+
 def test_edge_cases(g):
     # nev == n: the initial block spans the whole space
     A = wl.laplace2d_5pt(4)
