@@ -213,7 +213,7 @@ def test_cg_fp64_matches_oracle(g, maxit):
     assert np.max(np.abs(host(D) - ref)) < 1e-10 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("k", [1, 7, 26, 50, 100])
+@pytest.mark.parametrize("k", [1, 7, 26, 33, 40, 50, 64, 100])
 def test_cg_fp64_block_widths(g, k):
     """Every stored-width layout of the CG vectors (flat kernels with 1 to 13
     slots per thread, and the row-group kernels beyond), ragged row counts."""
@@ -238,6 +238,49 @@ def test_cg_plane_blocked_spmm_order(g, precision):
     ref, _ = orc.cg_columnwise(A, "diag", d, 40.0, R, maxit=3, rel_tol=0.0)
     tol = 1e-12 if precision == "fp64" else 1e-4
     assert np.max(np.abs(host(D) - ref)) < tol * np.max(np.abs(ref))
+
+
+def test_cg_fp64_plane_blocked_order_full_width(g):
+    """The FP64 CG product at the benchmark's block width (50 columns, 32
+    lanes per row) over the plane-blocked row order of a 48^3 grid."""
+    A = wl.laplace3d_7pt(48)
+    d = wl.diag_uniform(A.n)
+    R = RNG.standard_normal((A.n, 50))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), dev(d), 40.0, dev(R), maxit=3, rel_tol=0.0)
+    ref, _ = orc.cg_columnwise(A, "diag", d, 40.0, R, maxit=3, rel_tol=0.0)
+    assert np.max(np.abs(host(D) - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def arrow_matrix(m):
+    """A 2D five-point Laplacian (m x m) plus rows 0 and n // 2 coupled to
+    every row with weight -1e-3 (and the diagonal raised to keep it SPD by
+    diagonal dominance): the row blocks holding those two rows carry more
+    nonzeros than the SpMM's LDS pattern stage (1 024), so they read the
+    pattern from global memory."""
+    L = wl.laplace2d_5pt(m)
+    n = L.n
+    D = L.to_dense()
+    for h in (0, n // 2):
+        D[h, :] -= 1e-3
+        D[:, h] -= 1e-3
+        D[h, h] += 2e-3
+    D += np.diag(np.abs(D).sum(axis=1) - np.abs(np.diag(D)) - np.diag(D) + 4.0 * (np.abs(np.diag(D)) > 0))
+    rows, cols = np.nonzero(D)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return wl.Csr(n, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), D[rows, cols].astype(np.float64))
+
+
+@pytest.mark.parametrize("k", [8, 50])
+def test_cg_fp64_long_rows(g, k):
+    A = arrow_matrix(40)
+    assert np.max(np.diff(A.rowptr)) == A.n
+    R = RNG.standard_normal((A.n, k))
+    D, its = g.cg(g.DeviceCsr.from_csr(A), None, 0.0, dev(R), maxit=5, rel_tol=0.0)
+    ref, _ = orc.cg_columnwise(A, "identity", None, 0.0, R, maxit=5, rel_tol=0.0)
+    assert np.max(np.abs(host(D) - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("k", [13, 50, 100])
