@@ -1,9 +1,11 @@
 // Dense symmetric eigensolver on the device for the reduced Rayleigh-Ritz
 // problem of STEP 3 (Section 3.2; the paper calls LAPACK dsyevx on the host).
 //
-//   1. Householder reduction of the n x n matrix to tridiagonal form T by one
-//      work-group, one pass over the lower triangle per step (the matrix
-//      stays in L2; vectors in LDS).
+//   1. Householder reduction of the n x n matrix to tridiagonal form T, one
+//      pass over the lower triangle per step (vectors in LDS): by one
+//      work-group, or from order 257 on by eight work-groups of one
+//      cooperative launch that split the rows and meet at one grid barrier
+//      per step.
 //   2. The nwant smallest eigenvalues of T by multisection: one wave per
 //      eigenvalue, 64 Sturm counts per round (one per lane).
 //   3. Their eigenvectors by inverse iteration with a partially pivoted LU of
@@ -18,6 +20,7 @@
 //
 // Every step is deterministic (fixed reduction orders, counter-based start
 // vectors).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -293,6 +296,212 @@ __global__ __launch_bounds__(TRI_T) void k_tridiag(int n, double *__restrict__ a
     }
 }
 
+// The same reduction spread over TRI_G work-groups of one cooperative launch.
+// Rows of the trailing block are dealt to the G * TRI_W waves of the grid in
+// turn (RU rows at a time); a work-group's pass applies the pending rank-2
+// update to its own rows of the lower triangle and writes its partial of
+// y = C v (the row sums of its rows and the column contributions of its rows
+// to every column) to its slot of yp.  After one grid barrier per step every
+// work-group sums the G partials in slot order and forms w, the updated next
+// column and the next reflector itself (the same values in every
+// work-group); work-group 0 writes d, e, tau and the reflector into the
+// upper triangle, which no step reads.  The partials alternate between two
+// buffers, so a work-group still summing one step's partials is never
+// overwritten by another's next pass.  Output as k_tridiag's.
+constexpr int TRI_G = 8;
+
+template <bool UPD, int NS, int RU, int SB, int CR>
+__device__ __forceinline__ void tri_pass_mw(int n, double *a, int64_t lda, int r0, const double *sv,
+                                            const double *sw, const double *vn, double *sy, double *comb,
+                                            double *yp) {
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int gw = blockIdx.x * TRI_W + wave, nw = gridDim.x * TRI_W;
+    const int mm = n - r0;
+    for (int r = tid; r < mm; r += TRI_T) sy[r0 + r] = 0.0;
+    __syncthreads();
+    double part[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) part[t] = 0.0;
+    for (int rb = gw * RU; rb < mm; rb += nw * RU) {
+        const int nsl = min(rb + RU - 1, mm - 1) / 64 + 1;
+        double acc[RU], vi[RU], wi[RU], vni[RU];
+        double *rows[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int i = min(r0 + rb + u, n - 1);
+            acc[u] = 0.0;
+            vi[u] = UPD ? sv[i] : 0.0;
+            wi[u] = UPD ? sw[i] : 0.0;
+            vni[u] = vn[i];
+            rows[u] = a + (int64_t)i * lda + r0;
+        }
+#pragma unroll
+        for (int t0 = 0; t0 < NS; t0 += SB) {
+            if (t0 < nsl) {
+                double x[SB][RU];
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                    const int t = t0 + b;
+                    if (t < NS && t < nsl) {
+                        const int rc = min(lane + 64 * t, mm - 1);
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) x[b][u] = rows[u][rc];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                    const int t = t0 + b;
+                    if (t < NS && t < nsl) {
+                        const int r = lane + 64 * t;
+                        const int rc = min(r, mm - 1);
+                        const double swr = UPD ? sw[r0 + rc] : 0.0, svr = UPD ? sv[r0 + rc] : 0.0;
+                        const double vnr = vn[r0 + rc];
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) {
+                            const int ri = rb + u;
+                            const bool in = ri < mm && r <= ri;
+                            double xv = x[b][u];
+                            if (UPD) {
+                                xv -= vi[u] * swr + wi[u] * svr;
+                                if (in) rows[u][r] = xv;
+                            }
+                            xv = in ? xv : 0.0;
+                            acc[u] += xv * vnr;
+                            const double xp = r < ri ? xv : 0.0;
+                            part[t] += xp * vni[u];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const double s = wsum(acc[u]);
+            if (lane == 0 && rb + u < mm) sy[r0 + rb + u] = s;
+        }
+    }
+    constexpr int NST = TRI_W / CR;
+    for (int stage = NST - 1; stage >= 0; --stage) {
+        if (wave / CR == stage) {
+            double *c = comb + (int64_t)(wave % CR) * n;
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const int r = lane + 64 * t;
+                if (r < mm) c[r] = (stage == NST - 1) ? part[t] : c[r] + part[t];
+            }
+        }
+        __syncthreads();
+    }
+    for (int r = tid; r < mm; r += TRI_T) {
+        double y = sy[r0 + r];
+#pragma unroll
+        for (int q = 0; q < CR; ++q) y += comb[(int64_t)q * n + r];
+        yp[r0 + r] = y;
+    }
+    __syncthreads();
+}
+
+// y[r0..n-1] = the sum of the G partials in slot order
+__device__ __forceinline__ void tri_gather(int n, int r0, const double *yp, double *sy) {
+    const int G = gridDim.x;
+    for (int r = r0 + threadIdx.x; r < n; r += TRI_T) {
+        double y = 0.0;
+        for (int g = 0; g < G; ++g) y += yp[(int64_t)g * n + r];
+        sy[r] = y;
+    }
+    __syncthreads();
+}
+
+template <int NS, int RU, int SB>
+__global__ __launch_bounds__(TRI_T) void k_tridiag_mw(int n, double *a, int64_t lda, double *__restrict__ d,
+                                                       double *__restrict__ e, double *__restrict__ tau,
+                                                       double *ypart) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    extern __shared__ double sm[];
+    double *svA = sm, *swA = sm + n, *svB = sm + 2 * n, *swB = sm + 3 * n, *sy = sm + 4 * n, *sx = sm + 5 * n;
+    constexpr int CR = tri_comb_rows(NS);
+    double *comb = sm + 6 * n;
+    __shared__ double red[2][TRI_W];
+    const int tid = threadIdx.x, g = blockIdx.x, G = gridDim.x;
+    const bool lead = g == 0;
+    if (n <= 2) {   // the same in every work-group: no barrier is reached
+        if (lead && tid == 0) {
+            d[0] = a[0];
+            if (n == 2) {
+                e[0] = a[lda];
+                d[1] = a[lda + 1];
+                tau[0] = 0.0;
+            }
+        }
+        return;
+    }
+    // reflector 0 from column 0 below the diagonal (the input is fully
+    // symmetric; work-group 0 overwrites row 0's upper part with it)
+    double sq = 0.0;
+    for (int i = 1 + tid; i < n; i += TRI_T) {
+        const double v = a[(int64_t)i * lda];
+        sx[i] = v;
+        sq += i >= 2 ? v * v : 0.0;
+    }
+    double t0, b0;
+    tri_reflector(n, 1, sx, svA, red[0], sq, t0, b0);
+    if (lead) {
+        for (int i = 1 + tid; i < n; i += TRI_T) a[i] = svA[i];
+        if (tid == 0) {
+            d[0] = a[0];
+            e[0] = b0;
+            tau[0] = t0;
+        }
+    }
+    int par = 0;
+    tri_pass_mw<false, NS, RU, SB, CR>(n, a, lda, 1, nullptr, nullptr, svA, sy, comb,
+                                       ypart + ((int64_t)par * G + g) * n);
+    grid.sync();
+    tri_gather(n, 1, ypart + (int64_t)par * G * n, sy);
+    tri_w(n, 1, t0, sy, svA, swA, red[1]);
+    double *sv = svA, *sw = swA, *sv2 = svB, *sw2 = swB;
+    for (int k = 0; k + 4 <= n; ++k) {
+        const int k1 = k + 1;
+        par ^= 1;
+        // updated column k1 below the diagonal and the diagonal entry
+        double sq1 = 0.0;
+        for (int i = k1 + 1 + tid; i < n; i += TRI_T) {
+            const double v = a[(int64_t)i * lda + k1] - (sv[i] * sw[k1] + sw[i] * sv[k1]);
+            sx[i] = v;
+            sq1 += i >= k1 + 2 ? v * v : 0.0;
+        }
+        const double dk1 = a[(int64_t)k1 * lda + k1] - (sv[k1] * sw[k1] + sw[k1] * sv[k1]);
+        double t1, b1;
+        tri_reflector(n, k1 + 1, sx, sv2, red[0], sq1, t1, b1);
+        if (lead) {
+            for (int i = k1 + 1 + tid; i < n; i += TRI_T) a[(int64_t)k1 * lda + i] = sv2[i];
+            if (tid == 0) {
+                d[k1] = dk1;
+                e[k1] = b1;
+                tau[k1] = t1;
+            }
+        }
+        tri_pass_mw<true, NS, RU, SB, CR>(n, a, lda, k1 + 1, sv, sw, sv2, sy, comb,
+                                          ypart + ((int64_t)par * G + g) * n);
+        grid.sync();
+        tri_gather(n, k1 + 1, ypart + (int64_t)par * G * n, sy);
+        tri_w(n, k1 + 1, t1, sy, sv2, sw2, red[1]);
+        double *tv = sv, *tw = sw;
+        sv = sv2;
+        sw = sw2;
+        sv2 = tv;
+        sw2 = tw;
+    }
+    // pending update of the last reflector on the trailing 2 x 2 block
+    if (lead && tid == 0) {
+        const int p = n - 2, q = n - 1;
+        d[p] = a[(int64_t)p * lda + p] - (sv[p] * sw[p] + sw[p] * sv[p]);
+        e[p] = a[(int64_t)q * lda + p] - (sv[q] * sw[p] + sw[q] * sv[p]);
+        d[q] = a[(int64_t)q * lda + q] - (sv[q] * sw[q] + sw[q] * sv[q]);
+        tau[p] = 0.0;
+    }
+}
+
 // Gershgorin interval, norm bound and pivot floor of T, as every wave of the
 // later kernels computes them (identically).
 struct TBounds {
@@ -543,7 +752,8 @@ __global__ __launch_bounds__(256) void k_ns_coef(int m, double *__restrict__ G, 
 }  // namespace
 
 hipError_t DenseEigWork::ensure(int n, int nwant) {
-    const size_t need = (size_t)n * n + 3 * (size_t)n + 32 + 3 * (size_t)n * nwant + (size_t)nwant * nwant + 64;
+    const size_t need = (size_t)n * n + 3 * (size_t)n + 32 + 3 * (size_t)n * nwant + (size_t)nwant * nwant + 64 +
+                        2 * (size_t)TRI_G * n + 64;
     if (need <= cap) return hipSuccess;
     if (buf) (void)hipFree(buf);
     buf = nullptr;
@@ -560,6 +770,44 @@ void DenseEigWork::release() {
     cap = 0;
 }
 
+// Householder reduction of the n x n matrix a (row-major, lda = n) to
+// tridiagonal form: orders from TRI_MW_MIN on by TRI_G cooperating
+// work-groups (one grid barrier per step), below that, or when the runtime
+// refuses the cooperative launch, by one work-group.  Measured per call
+// (one work-group against eight): orders 449-512 7.0 / 4.7 ms, 385-448
+// 5.7 / 4.0, 321-384 4.1 / 3.3, 257-320 2.9 / 2.7, 193-256 1.7 / 1.8.
+constexpr int TRI_MW_MIN = 257;
+static hipError_t tridiagonalize(int n, double *a, double *dg, double *off, double *tau, double *yp,
+                                 hipStream_t st) {
+    const int ns = (n + 63) / 64;   // column slots per lane
+    const size_t lds = sizeof(double) * (6 + tri_comb_rows(ns)) * n;
+    int64_t ldn = n;
+    if (n >= TRI_MW_MIN) {
+        void *args[] = {(void *)&n, (void *)&a, (void *)&ldn, (void *)&dg, (void *)&off, (void *)&tau, (void *)&yp};
+        hipError_t le = hipErrorInvalidValue;
+#define GCGE_TRI_MW(NSv, RUv, SBv)                                                                      \
+    if (ns == NSv)                                                                                       \
+        le = hipLaunchCooperativeKernel((const void *)k_tridiag_mw<NSv, RUv, SBv>, dim3(TRI_G), dim3(TRI_T), args, \
+                                        (unsigned)lds, st);
+        GCGE_TRI_MW(5, 1, 4) GCGE_TRI_MW(6, 1, 4) GCGE_TRI_MW(7, 1, 4) GCGE_TRI_MW(8, 1, 4)
+        GCGE_TRI_MW(9, 1, 2) GCGE_TRI_MW(10, 1, 2) GCGE_TRI_MW(11, 1, 2) GCGE_TRI_MW(12, 1, 2)
+#undef GCGE_TRI_MW
+        if (le == hipSuccess) return hipSuccess;
+        (void)hipGetLastError();   // refused: one work-group below
+    }
+    // rows per group and slots per load batch, the fastest measured at
+    // n = 300..500 (one row per group from 5 slots on; two rows would run
+    // out of registers from 7 on)
+#define GCGE_TRI(NSv, RUv, SBv)                                                                   \
+    if (ns == NSv)                                                                                 \
+        hipLaunchKernelGGL((k_tridiag<NSv, RUv, SBv>), dim3(1), dim3(TRI_T), lds, st, n, a, ldn, dg, off, tau);
+    GCGE_TRI(1, 2, 4) GCGE_TRI(2, 2, 4) GCGE_TRI(3, 2, 4) GCGE_TRI(4, 2, 4) GCGE_TRI(5, 1, 4)
+    GCGE_TRI(6, 1, 4) GCGE_TRI(7, 1, 4) GCGE_TRI(8, 1, 4) GCGE_TRI(9, 1, 2) GCGE_TRI(10, 1, 2)
+    GCGE_TRI(11, 1, 2) GCGE_TRI(12, 1, 2)
+#undef GCGE_TRI
+    return hipGetLastError();
+}
+
 hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, double *X, int64_t ldx,
                      DenseEigWork &dw, Workspace &ws, hipStream_t st) {
     if (n <= 0 || nwant <= 0) return hipSuccess;
@@ -574,23 +822,12 @@ hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, 
     double *X1 = Z + (size_t)n * nwant;          // row-major n x nwant scratch
     double *X2 = X1 + (size_t)n * nwant;         // row-major n x nwant scratch
     double *G = X2 + (size_t)n * nwant;          // nwant x nwant
+    double *yp = G + (size_t)nwant * nwant + 64;  // 2 x TRI_G x n partials of the cooperative reduction
     e = hipMemcpy2DAsync(a, sizeof(double) * n, A, sizeof(double) * lda, sizeof(double) * n, n,
                          hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    {
-        const int ns = (n + 63) / 64;   // column slots per lane
-        const size_t lds = sizeof(double) * (6 + tri_comb_rows(ns)) * n;
-        // rows per group and slots per load batch, the fastest measured at
-        // n = 300..500 (one row per group from 5 slots on; two rows would run
-        // out of registers from 7 on)
-#define GCGE_TRI(NSv, RUv, SBv)                                                                   \
-    if (ns == NSv)                                                                                 \
-        hipLaunchKernelGGL((k_tridiag<NSv, RUv, SBv>), dim3(1), dim3(TRI_T), lds, st, n, a, (int64_t)n, dg, off, tau);
-        GCGE_TRI(1, 2, 4) GCGE_TRI(2, 2, 4) GCGE_TRI(3, 2, 4) GCGE_TRI(4, 2, 4) GCGE_TRI(5, 1, 4)
-        GCGE_TRI(6, 1, 4) GCGE_TRI(7, 1, 4) GCGE_TRI(8, 1, 4) GCGE_TRI(9, 1, 2) GCGE_TRI(10, 1, 2)
-        GCGE_TRI(11, 1, 2) GCGE_TRI(12, 1, 2)
-#undef GCGE_TRI
-    }
+    e = tridiagonalize(n, a, dg, off, tau, yp, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bisect, dim3(nwant), dim3(64), sizeof(double) * 2 * n, st, n, dg, off, nwant, w);
     const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n + 64;
     hipLaunchKernelGGL(k_invit, dim3(nwant), dim3(64), inv_lds, st, n, dg, off, nwant, w, 1e-10, Z, (int64_t)n);
