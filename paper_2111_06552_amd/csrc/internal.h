@@ -130,6 +130,7 @@ struct CgState {
     T *rr, *rr0, *alpha, *beta;
     int *active, *its, *flags;   // flags[0] = columns still iterating, flags[1] = columns updated this iteration
     T *rz = nullptr;             // preconditioned CG: r . z per column (alpha = rz / pq, beta = rz_new / rz)
+    unsigned *done = nullptr;    // zeroed counter: alpha and beta then run one work-group per column
 };
 
 template <typename T>

@@ -1060,6 +1060,96 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const T *__restrict__ part, in
     }
 }
 
+// Column-parallel alpha and beta (CgState::done set): one work-group per
+// column sums that column's partials (thread t takes partials t, t + 256, ...
+// in order, then the waves in order) and updates the column as k_cg_alpha /
+// k_cg_beta do; the last work-group to finish (a counter it resets) counts
+// the active and updated columns into flags.  Each column's sum is one fixed
+// order, so results are reproducible.
+template <typename T>
+__device__ __forceinline__ T col_partial_sum(const T *__restrict__ part, int nparts, int c) {
+    __shared__ T red[4];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const T *base = part + (size_t)c * nparts;
+    T s = T(0);
+    for (int p = tid; p < nparts; p += 256) s += base[p];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// true in every thread of the work-group that finishes last (after its
+// column's writes, which the fence publishes)
+__device__ __forceinline__ bool last_of_grid(unsigned *done) {
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_alpha_c(const T *__restrict__ part, int nparts, int k, CgState<T> cs) {
+    const int c = blockIdx.x;
+    if (cs.flags[0] == 0) {
+        if (threadIdx.x == 0) cs.alpha[c] = T(0);
+    } else {
+        const T pq = col_partial_sum(part, nparts, c);
+        if (threadIdx.x == 0) {
+            T al = T(0);
+            if (cs.active[c]) {
+                if (pq > T(0)) {
+                    al = (cs.rz != nullptr ? cs.rz[c] : cs.rr[c]) / pq;
+                    cs.its[c] += 1;
+                } else {
+                    cs.active[c] = 0;   // p^T (A - theta B) p <= 0: freeze the column
+                }
+            }
+            cs.alpha[c] = al;
+        }
+    }
+    if (last_of_grid(cs.done) && threadIdx.x == 0) {
+        int live = 0, na = 0;
+        if (cs.flags[0] != 0)
+            for (int j = 0; j < k; ++j) {
+                live += (cs.alpha[j] != T(0)) ? 1 : 0;
+                na += cs.active[j];
+            }
+        cs.flags[0] = na;
+        cs.flags[1] = live;
+        *cs.done = 0u;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_beta_c(const T *__restrict__ part, int nparts, int k, T tol2,
+                                                   CgState<T> cs) {
+    if (cs.flags[1] == 0) return;   // the same in every work-group: the counter is not touched
+    const int c = blockIdx.x;
+    const T rrn = col_partial_sum(part, nparts, c);
+    if (threadIdx.x == 0) {
+        T be = T(0);
+        if (cs.alpha[c] != T(0)) {
+            be = rrn / cs.rr[c];
+            cs.rr[c] = rrn;
+            if (rrn <= tol2 * cs.rr0[c]) cs.active[c] = 0;
+        }
+        if (cs.rz == nullptr) cs.beta[c] = be;   // preconditioned: beta comes from r . z
+    }
+    if (last_of_grid(cs.done) && threadIdx.x == 0) {
+        int na = 0;
+        for (int j = 0; j < k; ++j) na += cs.active[j];
+        cs.flags[0] = na;
+        *cs.done = 0u;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pcg_rz(const T *__restrict__ part, int nparts, int k, int init,
                                                  CgState<T> cs) {
@@ -1146,7 +1236,8 @@ hipError_t cg_init_finish(const T *part, int nparts, int k, CgState<T> cs, hipSt
 
 template <typename T>
 hipError_t cg_alpha(const T *part, int nparts, int k, CgState<T> cs, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_alpha<T>, dim3(1), dim3(1024), 0, st, part, nparts, k, cs);
+    if (cs.done != nullptr && k > 0) hipLaunchKernelGGL(k_cg_alpha_c<T>, dim3(k), dim3(256), 0, st, part, nparts, k, cs);
+    else hipLaunchKernelGGL(k_cg_alpha<T>, dim3(1), dim3(1024), 0, st, part, nparts, k, cs);
     return hipGetLastError();
 }
 
@@ -1184,7 +1275,9 @@ hipError_t cg_update_r(int64_t n, int k, const T *q, T *r, int64_t ld, T *part, 
 template <typename T>
 hipError_t cg_beta(const T *part, int nparts, int k, double rel_tol, CgState<T> cs, hipStream_t st) {
     const T tol2 = (T)(rel_tol * rel_tol);
-    hipLaunchKernelGGL(k_cg_beta<T>, dim3(1), dim3(1024), 0, st, part, nparts, k, tol2, cs);
+    if (cs.done != nullptr && k > 0)
+        hipLaunchKernelGGL(k_cg_beta_c<T>, dim3(k), dim3(256), 0, st, part, nparts, k, tol2, cs);
+    else hipLaunchKernelGGL(k_cg_beta<T>, dim3(1), dim3(1024), 0, st, part, nparts, k, tol2, cs);
     return hipGetLastError();
 }
 

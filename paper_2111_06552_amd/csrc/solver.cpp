@@ -490,7 +490,10 @@ int gcge_handle_s::ensure_buffers(int bs, int capx, int prec, int hist) {
         A((void **)&mval32, sizeof(float) * std::max<int64_t>(op.nnz, 1));
         for (int i = 0; i < (prec >= 2 ? 5 : 4); ++i) A((void **)&cg32[i], sizeof(float) * n * ldB);
     }
+    // eight per-column slots, then the counter of the column-parallel
+    // alpha / beta kernels (zeroed below; each use leaves it zero)
     A(&cgmem, 8 * sizeof(double) * (ldB + 16) + 64);
+    if (e == hipSuccess) e = hipMemset((char *)cgmem + 8 * sizeof(double) * (ldB + 16), 0, 64);
     // Rayleigh-Ritz state: Abar of order at most capx + 2 bs (X_u, P, W)
     const int dmax = capx + 2 * bs + 8;
     const size_t d2 = (size_t)dmax * dmax, db = (size_t)dmax * ldB;
@@ -604,6 +607,7 @@ int gcge_handle_s::do_cg(double theta, const double *R, int64_t ldr, int k, cons
     if (!mixed) {
         CgState<double> cs{(double *)cm, (double *)(cm + slot), (double *)(cm + 2 * slot), (double *)(cm + 3 * slot),
                            (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
+        cs.done = (unsigned *)(cm + 8 * slot);
         CgRunner<double> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
         runner.hist = (double *)cghist;
         runner.hist_slots = cghist_slots;
@@ -638,6 +642,7 @@ int gcge_handle_s::do_cg(double theta, const double *R, int64_t ldr, int k, cons
     if (e != hipSuccess) return hipfail(e, "upload");
     CgState<float> cs{(float *)cm, (float *)(cm + slot), (float *)(cm + 2 * slot), (float *)(cm + 3 * slot),
                       (int *)(cm + 4 * slot), (int *)(cm + 5 * slot), (int *)(cm + 6 * slot)};
+    cs.done = (unsigned *)(cm + 8 * slot);
     CgRunner<float> runner{op.n, ws, st, pinned_flag, ev, err, &prof};
     runner.hist = (float *)cghist;
     runner.hist_slots = cghist_slots;
@@ -1395,18 +1400,21 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
         if (e == hipSuccess) {
             const size_t slot = sizeof(double) * (ld + 16);
             char *c8 = (char *)cm;
-            if (!mixed) {
+            unsigned *done = (unsigned *)(c8 + 8 * slot);   // counter of the column-parallel alpha / beta
+            e = hipMemsetAsync(done, 0, 64, st);
+            if (e == hipSuccess && !mixed) {
                 double *v = (double *)vecs;
                 CgState<double> cs{(double *)c8, (double *)(c8 + slot), (double *)(c8 + 2 * slot),
                                    (double *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                    (int *)(c8 + 6 * slot)};
+                cs.done = done;
                 CgRunner<double> runner{n, C.ws, st, nullptr, nullptr, err};
                 DevCsr<double> M = op.csr_of(m64);
                 rc = runner.run(M, R, ldr, nullptr, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld, v + 3 * n * ld, ld, cs,
                                 nullptr);
                 if (!rc) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
                 if (!rc && e == hipSuccess && its) e = C.stg.download(its, cs.its, sizeof(int) * k);
-            } else {
+            } else if (e == hipSuccess) {
                 float *v = (float *)vecs;
                 // RHS scaled to unit columns; delta scaled back
                 std::vector<double> rn(k), bn(k), sc(k);
@@ -1431,6 +1439,7 @@ extern "C" int gcge_cg(const gcge_csr *A, int b_kind, const void *B, double thet
                     CgState<float> cs{(float *)c8, (float *)(c8 + slot), (float *)(c8 + 2 * slot),
                                       (float *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                       (int *)(c8 + 6 * slot)};
+                    cs.done = done;
                     CgRunner<float> runner{n, C.ws, st, nullptr, nullptr, err};
                     DevCsr<float> M = op.csr_of(m32);
                     rc = runner.run(M, R, ldr, dsc, k, maxit, rel_tol, v, v + n * ld, v + 2 * n * ld, v + 3 * n * ld,
@@ -1552,10 +1561,13 @@ extern "C" int gcge_pcg(const gcge_csr *A, gcge_amg M, const double *R, int64_t 
             CgState<double> cs{(double *)c8, (double *)(c8 + slot), (double *)(c8 + 2 * slot),
                                (double *)(c8 + 3 * slot), (int *)(c8 + 4 * slot), (int *)(c8 + 5 * slot),
                                (int *)(c8 + 6 * slot), (double *)(c8 + 7 * slot)};
+            cs.done = (unsigned *)(c8 + 8 * slot);
+            e = hipMemsetAsync(cs.done, 0, 64, st);
             CgRunner<double> runner{n, C.ws, st, nullptr, nullptr, err};
-            rc = runner.run_pcg(op.csr_of(m64), M->amg, R, ldr, nullptr, k, maxit, rel_tol, v, v + n * ld,
-                                v + 2 * n * ld, v + 3 * n * ld, v + 4 * n * ld, ld, cs, nullptr);
-            if (!rc) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
+            if (e == hipSuccess)
+                rc = runner.run_pcg(op.csr_of(m64), M->amg, R, ldr, nullptr, k, maxit, rel_tol, v, v + n * ld,
+                                    v + 2 * n * ld, v + 3 * n * ld, v + 4 * n * ld, ld, cs, nullptr);
+            if (!rc && e == hipSuccess) e = copy_cols<double, double>(n, k, v, ld, delta, ldd, nullptr, st);
             if (!rc && e == hipSuccess && its) e = C.stg.download(its, cs.its, sizeof(int) * k);
         }
         if (e == hipSuccess) e = C.stg.sync();
