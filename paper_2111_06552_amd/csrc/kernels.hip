@@ -679,6 +679,66 @@ __global__ __launch_bounds__(256) void k_cg_init(int64_t n, int k, const double 
 
 
 
+// k_cg_init in the layout of k_cg_update_r_pk: thread t owns vector column t
+// mod ldv of row offset t / ldv, U rows per step; r and p (and x = 0) are
+// written as 16-byte vectors (padding columns of a partial vector get 0), the
+// RHS is read with scalar loads (R may start at any column).
+template <typename T, int V, int U>
+__global__ __launch_bounds__(256) void k_cg_init_pk(int64_t n, int ldv, int k, const double *__restrict__ R,
+                                                    int64_t ldr, const double *__restrict__ rscale,
+                                                    T *__restrict__ r, T *__restrict__ p, T *__restrict__ x,
+                                                    T *__restrict__ part) {
+    __shared__ T sh[256 * V];
+    const int tid = threadIdx.x;
+    const int RW = 256 / ldv;
+    const int ro = tid / ldv, c0 = (tid % ldv) * V;
+    const bool act = ro < RW && c0 < k;
+    const int64_t ld = (int64_t)ldv * V;
+    double sc[V];
+    T acc[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const bool on = act && c0 + e < k;
+        sc[e] = on ? (rscale != nullptr ? rscale[c0 + e] : 1.0) : 0.0;
+        acc[e] = T(0);
+    }
+    const RowWalk rw{(int64_t)blockIdx.x * RW * U, n, (int64_t)gridDim.x * RW * U};
+    if (act) {
+        for (int64_t row0 = rw.first; row0 < rw.end; row0 += rw.stride) {
+            double rv[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = min(row0 + u * RW + ro, n - 1);   // clamped: always in bounds
+#pragma unroll
+                for (int e = 0; e < V; ++e) rv[u][e] = c0 + e < k ? R[row * ldr + c0 + e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = row0 + u * RW + ro;
+                if (row >= n) continue;
+                Vec<T, V> v, z;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v.v[e] = (T)(rv[u][e] * sc[e]);
+                    z.v[e] = T(0);
+                    if (c0 + e < k) acc[e] = fma(v.v[e], v.v[e], acc[e]);
+                }
+                vst<T, V>(r + row * ld + c0, v);
+                vst<T, V>(p + row * ld + c0, v);
+                if (x != nullptr) vst<T, V>(x + row * ld + c0, z);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) sh[tid * V + e] = acc[e];
+    __syncthreads();
+    for (int c = tid; c < k; c += 256) {
+        T sum = T(0);
+        for (int o = 0; o < RW; ++o) sum += sh[(o * ldv + c / V) * V + c % V];
+        part[(size_t)c * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
 // Vector forms of the two CG update passes (16-byte accesses; same layout
 // conditions as k_spmms).
 template <typename T, int G, int V>
@@ -1213,6 +1273,13 @@ hipError_t cg_init(const double *R, int64_t ldr, const double *rscale, int k, in
                    int64_t ld, T *part, int *nparts, CgState<T> cs, hipStream_t st) {
     (void)cs;
     if (k > 128) return hipErrorInvalidValue;
+    constexpr int V = 16 / sizeof(T);
+    if (ld % V == 0 && (k + V - 1) / V * V <= ld && ld <= 64 * V && aligned16(r) && aligned16(p) && aligned16(x)) {
+        const int ldv = (int)(ld / V);
+        const int64_t units = (n + 4 * (256 / ldv) - 1) / (4 * (256 / ldv));
+        GCGE_ROW_GO((k_cg_init_pk<T, V, 4>), units, nparts, n, ldv, k, R, ldr, rscale, r, p, x, part);
+        return hipGetLastError();
+    }
     const int G = k <= 16 ? 16 : k <= 32 ? 32 : 64, CT = k <= 64 ? 1 : 2;
     const int64_t units = (n + 256 / G - 1) / (256 / G);
     int g = 0;
