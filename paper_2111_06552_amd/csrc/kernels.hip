@@ -2419,8 +2419,7 @@ hipError_t phat_init(int dim, int nx, const double *xhat, int shift, int n_old, 
 
 // Gram-Schmidt among the columns of pt (dim x nn, ld nn) in one work-group:
 // column j is orthogonalized against the columns kept so far (twice; each
-// pass takes all coefficients against the kept columns at once, reading the
-// kept columns a row of phat at a time across a wave's lanes), then kept
+// pass takes all coefficients against the kept columns at once), then kept
 // (normalized, at the next free column of phat) when its norm exceeds
 // drop_tol times its norm before the projections against xhat, nrm0[j].
 // Columns of phat (dim x n_new, ld n_new) past the kept ones are zeroed; *np
@@ -2432,7 +2431,6 @@ __global__ __launch_bounds__(PHAT_T) void k_phat_mgs(int dim, int nn, const doub
                                                      double *__restrict__ phat, int n_new, int *np_out) {
     extern __shared__ double v[];
     __shared__ double cf[128];
-    __shared__ double cfw[PHAT_T / 64][128];
     __shared__ double red[PHAT_T / 64];
     __shared__ int s_np;
     const int t = threadIdx.x, wave = t / 64, lane = t % 64, nw = PHAT_T / 64;
@@ -2443,33 +2441,17 @@ __global__ __launch_bounds__(PHAT_T) void k_phat_mgs(int dim, int nn, const doub
         __syncthreads();
         const int np = s_np;
         for (int pass = 0; pass < 2 && np > 0; ++pass) {
-            // cf[q] = phat[:, q] . v: wave w takes rows w, w + nw, ..., lane
-            // l the kept columns l and l + 64 (a row of phat is one coalesced
-            // read); the waves' partials are added in wave order
-            double c0 = 0.0, c1 = 0.0;
-            for (int i = wave; i < dim; i += nw) {
-                const double vi = v[i];
-                const double *row = phat + (int64_t)i * n_new;
-                if (lane < np) c0 += row[lane] * vi;
-                if (lane + 64 < np) c1 += row[lane + 64] * vi;
-            }
-            cfw[wave][lane] = c0;
-            cfw[wave][lane + 64] = c1;
-            __syncthreads();
-            for (int q = t; q < np; q += PHAT_T) {
-                double c = 0.0;
-                for (int w = 0; w < nw; ++w) c += cfw[w][q];
-                cf[q] = c;
+            for (int q = wave; q < np; q += nw) {   // cf[q] = phat[:, q] . v, one wave per coefficient
+                double s = 0.0;
+                for (int i = lane; i < dim; i += 64) s += phat[(int64_t)i * n_new + q] * v[i];
+                s = wave_sum(s);
+                if (lane == 0) cf[q] = s;
             }
             __syncthreads();
-            // v[i] -= sum_q cf[q] phat[i, q]: a wave per row, lanes over q
-            for (int i = wave; i < dim; i += nw) {
-                const double *row = phat + (int64_t)i * n_new;
-                double x = 0.0;
-                if (lane < np) x += cf[lane] * row[lane];
-                if (lane + 64 < np) x += cf[lane + 64] * row[lane + 64];
-                x = wave_sum(x);
-                if (lane == 0) v[i] -= x;
+            for (int i = t; i < dim; i += PHAT_T) {
+                double x = v[i];
+                for (int q = 0; q < np; ++q) x -= cf[q] * phat[(int64_t)i * n_new + q];
+                v[i] = x;
             }
             __syncthreads();
         }
