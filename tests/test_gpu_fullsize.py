@@ -116,6 +116,34 @@ def test_config2_multigrid_inner_solve_full(g, config2, prec):
     check_sampled(A, "diag", B, lam, X, sampled_columns(p["nev"], 12, 73), p["tol"])
 
 
+def test_config2_other_initial_block_same_spectrum_full(g, config2):
+    """A second FP64 solve from an unrelated random initial block (another
+    SplitMix64 seed) converges to the same 200 eigenvalues: a pair missed
+    inside a cluster would have to be missed from both starting subspaces."""
+    A, B, p, out = config2
+    lam64 = out["fp64"][0]
+    Ad = g.DeviceCsr.from_csr(A)
+    Bd = torch.as_tensor(B, dtype=torch.float64, device="cuda")
+    with g.Solver(Ad, Bd, p["nev"], p["tol"], block_size=p["block_size"], seed=7) as s:
+        lam, X, st = s.solve()
+        lam, X = lam.numpy().copy(), host(X)
+    print(f"[config2 seed 7] {st['iterations']} iterations, max residual {st['max_rel_residual']:.2e}", flush=True)
+    assert st["status"] == 0 and st["nconv"] == p["nev"]
+    assert np.max(np.abs(lam - lam64) / np.abs(lam64)) < 1e-10
+    # the leading m vectors of this solve lie in the span of the other's 200:
+    # the cosines of the principal angles (singular values of X_7[:, :m]^T D
+    # X_1) are 1 up to the residual over the gap that separates lambda_m from
+    # the rest of the spectrum (at least lambda_200 - lambda_m; a factor 10
+    # covers the norm constants for 0.5 <= D <= 1.5)
+    X1 = out["fp64"][1]
+    m = p["nev"] - 10
+    gap = lam64[-1] - lam64[m - 1]
+    sin_bound = 10 * np.sqrt(m) * p["tol"] * lam64[m - 1] / gap
+    sv = np.linalg.svd(X[:, :m].T @ (B[:, None] * X1), compute_uv=False)
+    assert sv.max() < 1 + 1e-10, sv.max()
+    assert sv.min() >= np.sqrt(1 - min(1.0, sin_bound ** 2)) - 1e-12, (sv.min(), sin_bound)
+
+
 def test_config2_identity_B_closed_form_full(g):
     """128^3 Laplacian with B = I: the 200 smallest eigenvalues are known exactly
     (the 6-fold cluster 197-202 is cut by nev; eigenvalues are still unique)."""
