@@ -3,7 +3,7 @@
 //
 //   1. Householder reduction of the n x n matrix to tridiagonal form T, one
 //      pass over the lower triangle per step (vectors in LDS): by one
-//      work-group, or from order 257 on by eight work-groups of one
+//      work-group, or from order 305 on by eight work-groups of one
 //      cooperative launch that split the rows and meet at one grid barrier
 //      per step.
 //   2. The nwant smallest eigenvalues of T by multisection: one wave per
@@ -12,7 +12,8 @@
 //      T - lambda I; eigenvalues closer than a cluster tolerance are handled by
 //      one work-group in order, each vector orthogonalized against the earlier
 //      ones of its cluster (classical Gram-Schmidt, twice).
-//   4. Back-transformation by the Householder reflectors.
+//   4. Back-transformation by the Householder reflectors, one wave per
+//      column.
 //   5. Two Newton-Schulz steps X <- X (3 I - X^T X) / 2 with the block Gram
 //      and GEMM kernels, which restore orthonormality to rounding (inverse
 //      iteration leaves eps ||T|| / gap between vectors of distinct
@@ -810,9 +811,10 @@ void DenseEigWork::release() {
 // tridiagonal form: orders from TRI_MW_MIN on by TRI_G cooperating
 // work-groups (one grid barrier per step), below that, or when the runtime
 // refuses the cooperative launch, by one work-group.  Measured per call
-// (one work-group against eight): orders 449-512 7.0 / 4.7 ms, 385-448
-// 5.7 / 4.0, 321-384 4.1 / 3.3, 257-320 2.9 / 2.7, 193-256 1.7 / 1.8.
-constexpr int TRI_MW_MIN = 257;
+// (one work-group against eight): order 512 8.1 / 5.2 ms, 448 6.0 / 4.3,
+// 384 4.1 / 3.5, 352 3.4 / 3.1, 320 2.76 / 2.67, 288 2.22 / 2.35, 260
+// 1.83 / 2.07.
+constexpr int TRI_MW_MIN = 305;
 static hipError_t tridiagonalize(int n, double *a, double *dg, double *off, double *tau, double *yp,
                                  hipStream_t st) {
     const int ns = (n + 63) / 64;   // column slots per lane

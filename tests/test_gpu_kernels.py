@@ -419,7 +419,7 @@ def _check_dense_eig(g, A, nwant, ref=None):
 
 
 @pytest.mark.parametrize("n,nwant", [(1, 1), (2, 2), (3, 2), (4, 4), (5, 3), (17, 17), (64, 40), (65, 65), (200, 150),
-                                     (300, 200), (384, 384), (385, 100), (450, 350), (513, 300), (640, 64),
+                                     (300, 200), (310, 250), (384, 384), (385, 100), (450, 350), (513, 300), (640, 64),
                                      (700, 350), (768, 500)])
 def test_dense_eig_random_symmetric(g, n, nwant):
     M = RNG.standard_normal((n, n))
