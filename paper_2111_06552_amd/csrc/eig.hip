@@ -622,7 +622,13 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double *__restrict__ 
     while (j < nwant && w[j] - w[j - 1] <= ctol) ++j;
     extern __shared__ double sm[];
     double *u1 = sm, *u2 = sm + n, *u3 = sm + 2 * n, *ml = sm + 3 * n, *z = sm + 4 * n;
-    int *piv = (int *)(sm + 5 * n);
+    double *iu1 = sm + 5 * n, *sd = sm + 6 * n, *se = sm + 7 * n;   // 1 / u1; T staged in LDS
+    int *piv = (int *)(sm + 8 * n);
+    for (int r = lane; r < n; r += 64) {
+        sd[r] = d[r];
+        se[r] = r + 1 < n ? e[r] : 0.0;
+    }
+    __syncthreads();
     const double tiny = EPS * b.tnorm + b.pivmin;
     double sprev = -INFINITY;
     for (int mbr = i; mbr < j; ++mbr) {
@@ -630,12 +636,13 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double *__restrict__ 
         if (s <= sprev) s = sprev + 10.0 * EPS * b.tnorm;   // separate equal shifts
         sprev = s;
         if (lane == 0) {
-            // LU with partial pivoting of the tridiagonal T - s I
-            double ar = d[0] - s, br = (n > 1) ? e[0] : 0.0;
+            // LU with partial pivoting of the tridiagonal T - s I (T read
+            // from LDS; only ar and br are carried from step to step)
+            double ar = sd[0] - s, br = (n > 1) ? se[0] : 0.0;
             for (int r = 0; r + 1 < n; ++r) {
-                const double cr = e[r];                       // subdiagonal entry (r+1, r)
-                const double an = d[r + 1] - s;               // diagonal of row r+1
-                const double bn = (r + 2 < n) ? e[r + 1] : 0.0;   // (r+1, r+2)
+                const double cr = se[r];                      // subdiagonal entry (r+1, r)
+                const double an = sd[r + 1] - s;              // diagonal of row r+1
+                const double bn = se[r + 1];                  // (r+1, r+2); 0 past the end
                 if (fabs(ar) >= fabs(cr)) {
                     const double aa = (fabs(ar) < tiny) ? copysign(tiny, ar) : ar;
                     const double l = cr / aa;
@@ -667,21 +674,32 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double *__restrict__ 
             z[r] = 2.0 * ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
         }
         __syncthreads();
+        for (int r = lane; r < n; r += 64) iu1[r] = 1.0 / u1[r];
+        __syncthreads();
         for (int it = 0; it < 3; ++it) {
             if (lane == 0) {
-                // forward: row interchanges and L
+                // forward: row interchanges and L.  The value moving down
+                // (z[r] after the steps before) is carried in a register;
+                // z[r + 1] is still the input's, so every load of a step is
+                // independent of the carried value and can be issued early.
+                double c = z[0];
                 for (int r = 0; r + 1 < n; ++r) {
-                    if (piv[r]) {
-                        const double t = z[r];
-                        z[r] = z[r + 1];
-                        z[r + 1] = t;
-                    }
-                    z[r + 1] -= ml[r] * z[r];
+                    const double t = z[r + 1], l = ml[r];
+                    const bool sw = piv[r] != 0;
+                    z[r] = sw ? t : c;
+                    c = sw ? fma(-l, t, c) : fma(-l, c, t);
                 }
-                // back substitution with U
-                z[n - 1] /= u1[n - 1];
-                if (n >= 2) z[n - 2] = (z[n - 2] - u2[n - 2] * z[n - 1]) / u1[n - 2];
-                for (int r = n - 3; r >= 0; --r) z[r] = (z[r] - u2[r] * z[r + 1] - u3[r] * z[r + 2]) / u1[r];
+                z[n - 1] = c;
+                // back substitution with U, the two later unknowns carried in
+                // registers, the divisions by u1 as products with 1 / u1
+                double x1 = z[n - 1] * iu1[n - 1], x2 = 0.0;
+                z[n - 1] = x1;
+                for (int r = n - 2; r >= 0; --r) {
+                    const double x = (z[r] - u2[r] * x1 - u3[r] * x2) * iu1[r];
+                    z[r] = x;
+                    x2 = x1;
+                    x1 = x;
+                }
             }
             __syncthreads();
             // scale, then orthogonalize against the earlier cluster vectors (twice)
@@ -867,7 +885,7 @@ hipError_t dense_eig(int n, const double *A, int64_t lda, int nwant, double *w, 
     e = tridiagonalize(n, a, dg, off, tau, yp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bisect, dim3(nwant), dim3(64), sizeof(double) * 2 * n, st, n, dg, off, nwant, w);
-    const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n + 64;
+    const size_t inv_lds = sizeof(double) * 8 * n + sizeof(int) * n + 64;
     hipLaunchKernelGGL(k_invit, dim3(nwant), dim3(64), inv_lds, st, n, dg, off, nwant, w, 1e-10, Z, (int64_t)n);
     const int ns = (n + 63) / 64;
 #define GCGE_BTW(NSv)                                                                                  \
