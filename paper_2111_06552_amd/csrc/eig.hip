@@ -109,9 +109,11 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 constexpr int TRI_T = 1024, TRI_W = TRI_T / 64;
 static_assert(DENSE_EIG_MAX <= 12 * 64, "k_tridiag instances cover 12 column slots per lane");
 
-// Rows of the LDS buffer that combines the per-wave column sums: 8 (two
-// stages) while (6 + 8) n doubles fit in 64 KiB, else 4 (four stages).
-__host__ __device__ constexpr int tri_comb_rows(int ns) { return ns <= 8 ? 8 : 4; }
+// Rows of the LDS buffer that combines the per-wave column sums: one per
+// wave, so the 16 waves write their sums at once and one barrier precedes
+// the fixed-order sum; (6 + 16) n doubles are at most 135 KiB (order 768) of
+// the 160 KiB a work-group may hold.
+__host__ __device__ constexpr int tri_comb_rows(int) { return TRI_W; }
 
 // y = C v over the trailing block C = rows/cols r0..n-1, first applying the
 // pending update C -= sv sw^T + sw sv^T when UPD.  y goes to sy[r0..n-1].
